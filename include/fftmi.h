@@ -1,0 +1,169 @@
+/*
+ * fftmi.h -- C-ABI of libfftmi, an MI355X (gfx950) FFT -> filter -> IFFT library.
+ *
+ * The operations are those of "Construction of an algorithm in parallel for
+ * the Fast Fourier Transform" (Higuera, Sarria, Fonseca, Idarraga):
+ *
+ *   1D forward   (Section 2, eq. E2):  H[k] = (1/N) sum_j f[j] e^{-2 pi i kj/N}
+ *   1D inverse   (Section 3, eq. E3):  f[j] = sum_k c[k] e^{+2 pi i jk/N}   (unscaled)
+ *   2D forward   (Section 5, eq. 5):   F[u,v] = (1/N) sum_x sum_y f[x,y] e^{-2 pi i (ux/N + vy/M)}
+ *   2D inverse   (Section 5, 2D-IDFT): f[x,y] = (1/M) sum_u sum_v F[u,v] e^{+2 pi i (ux/N + vy/M)}
+ *   filter       (Section 6):          g = 2D-IDFT(H . 2D-DFT(f)), H real, scaling the
+ *                                      real and the imaginary part of each bin alike.
+ *
+ * Layout.  Complex data is complex64: interleaved (re, im) float32 pairs.  A 2D
+ * image is row-major [N rows][M columns]: x in [0, N) is the row index and y
+ * runs along a row; a batch of B images is [B][N][M], contiguous.  A batch of
+ * 1D signals is [B][N].  Every length must be a power of two (Section 6 pads
+ * images with zeros to the next power of two before transforming).
+ *
+ * Ownership.  Device buffers (inputs, outputs, workspace, masks) and the HIP
+ * stream belong to the caller; all pointers are device pointers unless stated
+ * otherwise, and a NULL stream is the default stream.  A plan owns its host
+ * metadata; twiddle tables (generated in FP64 on the host and rounded once to
+ * float32) are owned by the library, one set per device, and live until the
+ * process ends.  A plan is immutable after creation: executing one plan on
+ * several streams at once is allowed if each call has its own workspace.  A
+ * plan may only be executed on the device that was current at fft_plan time.
+ *
+ * Errors.  Every call returns FFT_OK or a negative status; nothing aborts or
+ * throws across this boundary.  All argument checks happen before any device
+ * work is enqueued, so a failed call leaves every buffer untouched.  Kernel
+ * launches are asynchronous: FFT_OK means "enqueued"; a fault inside a kernel
+ * shows up at the caller's next synchronisation.
+ */
+#ifndef FFTMI_H
+#define FFTMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+#define FFT_OK 0
+#define FFT_ERR_ARG (-1)         /* NULL pointer, bad rank/direction/flag, batch < 0 */
+#define FFT_ERR_SIZE (-2)        /* a length is not a power of two or is out of range */
+#define FFT_ERR_UNSUPPORTED (-3) /* valid request this library does not implement */
+#define FFT_ERR_WORKSPACE (-4)   /* workspace NULL while the plan needs one */
+#define FFT_ERR_HIP (-5)         /* a HIP runtime call failed (text via fft_strerror) */
+#define FFT_ERR_NOMEM (-6)       /* host or device allocation failed */
+#define FFT_ERR_STATE (-7)       /* plan used on another device, or wrong plan kind */
+
+/* ------------------------------------------------------------- directions */
+#define FFT_FORWARD (-1)     /* eq. E2 (1D) / eq. 5 (2D) */
+#define FFT_INVERSE (+1)     /* eq. E3 (1D) / 2D-IDFT (2D) */
+#define FFT_ADJ_FORWARD (-2) /* conjugate transpose of FFT_FORWARD */
+#define FFT_ADJ_INVERSE (+2) /* conjugate transpose of FFT_INVERSE */
+
+/* ------------------------------------------------------------------ flags */
+#define FFT_IN_C64 0x0u       /* input is complex64 (default) */
+#define FFT_IN_REAL_F32 0x1u  /* input is real float32; imaginary parts are zero */
+#define FFT_OUT_C64 0x0u      /* output is complex64 (default) */
+#define FFT_OUT_REAL_F32 0x2u /* output keeps only the real part, float32 */
+#define FFT_NORM_PAPER 0x0u   /* the paper's scale factors, listed above (default) */
+#define FFT_NORM_NUMPY 0x4u   /* forward unscaled, inverse 1/(number of points) */
+
+/* ------------------------------------------------------------------ masks */
+#define FFT_MASK_NONE 0        /* H = 1 */
+#define FFT_MASK_TENSOR_F32 1  /* H[u][v] = data[u*M + v], a float32 [N][M] device array */
+#define FFT_MASK_GAUSSIAN 2    /* H = exp(-r^2 / (2 sigma_f^2)) */
+#define FFT_MASK_BUTTERWORTH 3 /* H = 1 / (1 + (r / cutoff)^(2 order)) */
+#define FFT_MASK_DISC 4        /* eq. (filtro): H = 0 if sqrt((u-c1)^2+(v-c2)^2) <= b, else 1 */
+
+/* A real frequency-domain filter H over the bins (u, v) of an [N][M] spectrum
+ * (Section 6).  For the analytic kinds r is the radius in cycles per pixel on
+ * the unshifted frequency grid: f(k) = k/n for k < n/2, (k-n)/n otherwise, and
+ * r = sqrt(f(u)^2 + f(v)^2).  The disc works on raw bin indices (u, v); its
+ * paper reading puts (c1, c2) at (N/2, M/2). */
+typedef struct fft_mask {
+  int kind;           /* FFT_MASK_* */
+  const float* data;  /* FFT_MASK_TENSOR_F32 only (device pointer) */
+  double sigma_f;     /* FFT_MASK_GAUSSIAN */
+  double cutoff;      /* FFT_MASK_BUTTERWORTH */
+  int order;          /* FFT_MASK_BUTTERWORTH, >= 1 */
+  double b, c1, c2;   /* FFT_MASK_DISC */
+} fft_mask;
+
+typedef struct fftmi_plan* fft_plan_t;
+
+/* Create a plan for `batch` transforms of rank 1 (dims = {N}) or rank 2
+ * (dims = {N, M}) on the current HIP device.  Lengths: powers of two,
+ * 1 <= N <= 2^24 for rank 1 and 1 <= N, M <= 2^14 for rank 2.  batch >= 0
+ * (0 makes every call a no-op).  flags: FFT_IN_*, FFT_OUT_*, FFT_NORM_*.
+ * Errors: FFT_ERR_ARG, FFT_ERR_SIZE, FFT_ERR_NOMEM, FFT_ERR_HIP. */
+int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint32_t flags);
+
+/* Bytes of device workspace an exec/filter call on this plan needs (may be 0).
+ * The caller allocates it (256-byte alignment is enough) and may reuse it
+ * between calls on one stream. */
+int fft_workspace_size(fft_plan_t plan, size_t* bytes);
+
+/* One transform of the whole batch: in -> out, out of place (in == out is
+ * rejected with FFT_ERR_ARG).  Direction: FFT_FORWARD, FFT_INVERSE,
+ * FFT_ADJ_FORWARD or FFT_ADJ_INVERSE (Sections 2, 3 and 5).  Input and output
+ * element types follow the plan's flags. */
+int fft_exec(fft_plan_t plan, const void* in, void* out, void* workspace, int direction, void* stream);
+
+/* Section 6 on a rank-2 plan: out = 2D-IDFT(H . 2D-DFT(in)) for every image
+ * of the batch, one mask shared by the batch.  in may equal out.  The scale
+ * of the round trip is 1 under either FFT_NORM_* convention. */
+int fft2d_filter(fft_plan_t plan, const void* in, void* out, const fft_mask* mask, void* workspace,
+                 void* stream);
+
+/* One of the three passes of fft2d_filter, for callers that schedule (or
+ * time) the passes themselves; running stages 0, 1, 2 in order on one stream
+ * with the same workspace is fft2d_filter.
+ *   stage 0: FFT on rows (Section 5), in -> workspace; scale 1/N (eq. 5)
+ *   stage 1: FFT on columns, times H, inverse FFT on columns (eq. 5's column
+ *            sum, Section 6's product, the 2D-IDFT's column sum), in place in
+ *            the workspace; in, out are ignored
+ *   stage 2: inverse FFT on rows, workspace -> out; scale 1/M (2D-IDFT)
+ * Errors as fft2d_filter, plus FFT_ERR_ARG for another stage number. */
+int fft2d_filter_stage(fft_plan_t plan, int stage, const void* in, void* out, const fft_mask* mask,
+                       void* workspace, void* stream);
+
+/* fft2d_filter that also stores the forward spectrum X = 2D-DFT(in) of every
+ * image (complex64, in the plan's internal blocked layout, fft_spectrum_size
+ * bytes) for the mask gradient below.  Differentiable filtering: the mask is
+ * a learnable parameter (not in the paper; the transform pair is eq. 5 and
+ * the 2D-IDFT). */
+int fft2d_filter_save(fft_plan_t plan, const void* in, void* out, const fft_mask* mask, void* spectrum,
+                      void* workspace, void* stream);
+int fft_spectrum_size(fft_plan_t plan, size_t* bytes);
+
+/* Mask gradient of y = 2D-IDFT(m . X) for a rank-2 complex-input plan:
+ *   grad_mask[u][v] = sum_b Re( conj(X_b[u,v]) * (2D-IDFT^H g_b)[u,v] )
+ * where g_b = grad_y (complex64 [B][N][M], the gradient of a real loss with
+ * respect to y, as conj-Wirtinger "dL/dRe + i dL/dIm") and 2D-IDFT^H is the
+ * adjoint transform (scale 1/M under FFT_NORM_PAPER).  The batch sum runs in
+ * order b = 0..B-1 in float32; the result overwrites grad_mask (float32 [N][M]). */
+int fft2d_filter_mask_grad(fft_plan_t plan, const void* grad_y, const void* spectrum, float* grad_mask,
+                           void* workspace, void* stream);
+
+/* Ragged batch: `count` square images of power-of-two sizes sizes[i] (host
+ * array, 1 <= sizes[i] <= 2048), packed back to back in one buffer (image i
+ * starts at element sum_{j<i} sizes[j]^2).  The filter runs as one persistent
+ * launch with per-size schedules, captured in a HIP graph and replayed.
+ * flags: FFT_IN_* and FFT_OUT_*. */
+int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32_t flags);
+int fft2d_filter_ragged(fft_plan_t plan, const void* in_packed, void* out_packed, const fft_mask* mask,
+                        void* workspace, void* stream);
+
+/* Release a plan (and any graph it instantiated).  NULL is a no-op. */
+int fft_plan_destroy(fft_plan_t plan);
+
+/* Static text for a status code; the text of the last HIP failure is
+ * appended for FFT_ERR_HIP. */
+const char* fft_strerror(int code);
+
+/* Library version, e.g. 0x000100 for 0.1.0. */
+int fft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTMI_H */

@@ -1,0 +1,193 @@
+"""Tensor-level wrappers over the C-ABI.  PyTorch supplies device memory and the
+current HIP stream; every step of every transform runs in libfftmi's kernels.
+
+Conventions (the paper's, selected by norm="paper"): 1D forward carries 1/N
+(eq. E2), 1D inverse is unscaled (eq. E3); 2D forward carries 1/N with N the
+row count (eq. 5) and the 2D inverse 1/M (2D-IDFT).  norm="numpy" gives an
+unscaled forward and a 1/(number of points) inverse.
+"""
+import ctypes
+import threading
+
+import torch
+
+from . import _binding as B
+
+_NORM = {"paper": B.FFT_NORM_PAPER, "numpy": B.FFT_NORM_NUMPY}
+
+
+class Plan:
+    """Owns one fft_plan_t (created on the tensor's device)."""
+
+    def __init__(self, rank, dims, batch, flags=0, device=None, ragged_sizes=None):
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device.index)
+        with torch.cuda.device(self.device):
+            if ragged_sizes is not None:
+                self.h = B.fft_plan_ragged(ragged_sizes, flags)
+            else:
+                self.h = B.fft_plan(rank, dims, batch, flags)
+        self.rank, self.dims, self.batch, self.flags = rank, tuple(dims), batch, flags
+        self.workspace_bytes = B.fft_workspace_size(self.h)
+        self.spectrum_bytes = B.fft_spectrum_size(self.h) if rank == 2 and ragged_sizes is None else 0
+
+    def workspace(self):
+        n = max(self.workspace_bytes, 1)
+        return torch.empty(n, dtype=torch.uint8, device=self.device)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and B._lib is not None:
+            try:
+                B.fft_plan_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+
+_cache = {}
+_cache_lock = threading.Lock()
+
+
+def get_plan(rank, dims, batch, flags, device, ragged_sizes=None):
+    key = (rank, tuple(dims), int(batch), int(flags), device.index,
+           tuple(ragged_sizes) if ragged_sizes is not None else None)
+    with _cache_lock:
+        p = _cache.get(key)
+        if p is None:
+            p = Plan(rank, dims, batch, flags, device, ragged_sizes)
+            _cache[key] = p
+    return p
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _prep(x, allow_real=True):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if x.dtype == torch.complex64:
+        return x.contiguous(), B.FFT_IN_C64
+    if x.dtype == torch.float32 and allow_real:
+        return x.contiguous(), B.FFT_IN_REAL_F32
+    raise TypeError("expected complex64%s, got %s" % (" or float32" if allow_real else "", x.dtype))
+
+
+def transform(x, rank, direction, norm="paper", real_output=False):
+    """One batched transform over the last `rank` axes (fft_exec)."""
+    x, fin = _prep(x)
+    if x.dim() < rank:
+        raise ValueError("tensor has fewer than %d dims" % rank)
+    dims = tuple(x.shape[-rank:])
+    n = 1
+    for d in dims:
+        n *= d
+    batch = x.numel() // n if n else 0
+    flags = fin | _NORM[norm] | (B.FFT_OUT_REAL_F32 if real_output else 0)
+    plan = get_plan(rank, dims, batch, flags, x.device)
+    out = torch.empty(x.shape, dtype=torch.float32 if real_output else torch.complex64, device=x.device)
+    if batch == 0:
+        return out
+    ws = plan.workspace()
+    B.fft_exec(plan.h, _ptr(x), _ptr(out), _ptr(ws), direction, _stream(x.device))
+    return out
+
+
+def fft(x, norm="paper"):
+    """eq. E2 along the last axis: H[k] = (1/N) sum_j f[j] e^{-2 pi i kj/N}."""
+    return transform(x, 1, B.FFT_FORWARD, norm)
+
+
+def ifft(c, norm="paper", real_output=False):
+    """eq. E3 along the last axis: f[j] = sum_k c[k] e^{+2 pi i jk/N}."""
+    return transform(c, 1, B.FFT_INVERSE, norm, real_output)
+
+
+def fft2(x, norm="paper"):
+    """eq. 5 over the last two axes (factor 1/N, N rows)."""
+    return transform(x, 2, B.FFT_FORWARD, norm)
+
+
+def ifft2(F, norm="paper", real_output=False):
+    """2D-IDFT over the last two axes (factor 1/M, M columns)."""
+    return transform(F, 2, B.FFT_INVERSE, norm, real_output)
+
+
+def _mask_struct(mask, N, M, device):
+    """(fft_mask, keepalive) from a dict spec, a float32 [N][M] tensor or None."""
+    if mask is None:
+        return B.make_mask("none"), None
+    if isinstance(mask, torch.Tensor):
+        if mask.dtype != torch.float32 or tuple(mask.shape) != (N, M) or mask.device != device:
+            raise ValueError("tensor mask must be float32 [%d, %d] on %s" % (N, M, device))
+        m = mask.contiguous()
+        return B.make_mask("tensor", data_ptr=m.data_ptr()), m
+    spec = dict(mask)
+    kind = spec.pop("kind")
+    if kind == "disc":
+        spec.setdefault("c1", N / 2.0)
+        spec.setdefault("c2", M / 2.0)
+    return B.make_mask(kind, **spec), None
+
+
+def fft2d_filter(x, mask, norm="paper", real_output=False, spectrum=False):
+    """Section 6: 2D-IDFT(H . 2D-DFT(x)) over the last two axes of x.
+
+    mask: dict(kind="gaussian", sigma_f=...), dict(kind="butterworth",
+    cutoff=..., order=...), dict(kind="disc", b=..., c1=..., c2=...), a float32
+    [N][M] tensor, or None.  With spectrum=True also returns the saved forward
+    spectrum (internal layout) used by mask_grad.
+    """
+    x, fin = _prep(x)
+    N, M = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (N * M) if N * M else 0
+    flags = fin | _NORM[norm] | (B.FFT_OUT_REAL_F32 if real_output else 0)
+    plan = get_plan(2, (N, M), batch, flags, x.device)
+    out = torch.empty(x.shape, dtype=torch.float32 if real_output else torch.complex64, device=x.device)
+    mk, keep = _mask_struct(mask, N, M, x.device)
+    ws = plan.workspace()
+    st = _stream(x.device)
+    if spectrum:
+        spec = torch.empty(max(plan.spectrum_bytes, 1), dtype=torch.uint8, device=x.device)
+        if batch:
+            B.fft2d_filter_save(plan.h, _ptr(x), _ptr(out), mk, _ptr(spec), _ptr(ws), st)
+        return out, spec
+    if batch:
+        B.fft2d_filter(plan.h, _ptr(x), _ptr(out), mk, _ptr(ws), st)
+    del keep
+    return out
+
+
+def mask_grad(grad_y, spectrum, norm="paper"):
+    """sum_b Re(conj(X_b) . (2D-IDFT^H grad_y_b)) for a saved spectrum X."""
+    g, _ = _prep(grad_y, allow_real=False)
+    N, M = g.shape[-2], g.shape[-1]
+    batch = g.numel() // (N * M)
+    plan = get_plan(2, (N, M), batch, B.FFT_IN_C64 | _NORM[norm], g.device)
+    out = torch.empty((N, M), dtype=torch.float32, device=g.device)
+    ws = plan.workspace()
+    B.fft2d_filter_mask_grad(plan.h, _ptr(g), _ptr(spectrum), _ptr(out), _ptr(ws), _stream(g.device))
+    return out
+
+
+def filter_ragged(packed, sizes, mask, real_output=False):
+    """Ragged batch: square images of sizes[i]^2 packed back to back in one
+    1D tensor (float32 or complex64); returns the filtered images, packed."""
+    x, fin = _prep(packed)
+    sizes = [int(s) for s in sizes]
+    total = sum(s * s for s in sizes)
+    if x.numel() != total:
+        raise ValueError("packed tensor has %d elements, sizes need %d" % (x.numel(), total))
+    flags = fin | (B.FFT_OUT_REAL_F32 if real_output else 0)
+    plan = get_plan(0, (), len(sizes), flags, x.device, ragged_sizes=sizes)
+    out = torch.empty(total, dtype=torch.float32 if real_output else torch.complex64, device=x.device)
+    mk, keep = _mask_struct(mask, 1, 1, x.device) if not isinstance(mask, torch.Tensor) else (None, None)
+    if mk is None:
+        raise ValueError("ragged batches take an analytic mask")
+    ws = plan.workspace()
+    B.fft2d_filter_ragged(plan.h, _ptr(x), _ptr(out), mk, _ptr(ws), _stream(x.device))
+    return out

@@ -1,0 +1,448 @@
+// api.cpp -- the C-ABI of libfftmi: argument checks, plans, FP64 twiddle
+// generation, and the pass sequence of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <set>
+#include <string>
+#include <vector>
+
+#include "../../include/fftmi.h"
+#include "fft_schedule.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+using namespace fftmi;
+
+namespace fftmi {
+
+thread_local std::string g_err_text;
+
+int hip_fail(hipError_t e) {
+  g_err_text = std::string("HIP error: ") + hipGetErrorString(e);
+  return FFT_ERR_HIP;
+}
+
+// exp(-2 pi i t / n) evaluated in double precision from the exact integer
+// t mod n, rounded once to float (Table 2's factors Z).
+static float2 z_factor(int64_t t, int64_t n) {
+  t %= n;
+  if (t < 0) t += n;
+  const double a = 6.283185307179586476925286766559 * (double)t / (double)n;
+  return make_float2((float)std::cos(a), (float)-std::sin(a));
+}
+
+struct DevTables {
+  float2* blob = nullptr;
+  int64_t off[kMaxLog2Row + 1] = {};
+  std::map<int, std::pair<float2*, float2*>> fourstep;  // log2 N -> (lo, hi)
+  std::map<int, int> fourstep_h;
+};
+
+namespace {
+
+std::mutex g_mu;
+std::map<int, DevTables*> g_dev;
+std::mutex g_plan_mu;
+std::set<const fftmi_plan*> g_plans;
+
+int build_blobs(DevTables* t) {
+  std::vector<float2> host;
+  for (int lg = 0; lg <= kMaxLog2Row; ++lg) {
+    const int L = 1 << lg;
+    t->off[lg] = (int64_t)host.size();
+    for (int s = 1; s < num_stages(L); ++s) {
+      const int ns = stage_ns(L, s), r = stage_radix(L, s);
+      for (int k = 0; k < ns; ++k)
+        for (int q = 0; q < r; ++q) host.push_back(z_factor((int64_t)q * k, (int64_t)ns * r));
+    }
+    while (host.size() % 32) host.push_back(make_float2(0.f, 0.f));  // 256-byte aligned starts
+  }
+  void* d = nullptr;
+  hipError_t e = hipMalloc(&d, host.size() * sizeof(float2));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_NOMEM : hip_fail(e);
+  e = hipMemcpy(d, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e);
+  }
+  t->blob = static_cast<float2*>(d);
+  return FFT_OK;
+}
+
+}  // namespace
+
+// Tables of the current device (created on first use, kept until exit).
+int device_tables(int dev, DevTables** out) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it != g_dev.end()) {
+    *out = it->second;
+    return FFT_OK;
+  }
+  auto* t = new (std::nothrow) DevTables();
+  if (!t) return FFT_ERR_NOMEM;
+  int rc = build_blobs(t);
+  if (rc != FFT_OK) {
+    delete t;
+    return rc;
+  }
+  g_dev[dev] = t;
+  *out = t;
+  return FFT_OK;
+}
+
+const float2* blob_for(const DevTables* t, int log2L) { return t->blob + t->off[log2L]; }
+
+void plan_register(fftmi_plan* p) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans.insert(p);
+}
+bool plan_live(const fftmi_plan* p) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  return p && g_plans.count(p) && p->magic == kPlanMagic;
+}
+void plan_unregister(fftmi_plan* p) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  g_plans.erase(p);
+}
+
+// Two-level twiddles of the long transform: W_N^t = lo[t mod 2^h] * hi[t >> h].
+int fourstep_tables(DevTables* t, int log2N, const float2** lo, const float2** hi, int* h) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = t->fourstep.find(log2N);
+  if (it == t->fourstep.end()) {
+    const int hh = (log2N + 1) / 2;
+    const int64_t N = int64_t(1) << log2N, nlo = int64_t(1) << hh, nhi = N >> hh;
+    std::vector<float2> host((size_t)(nlo + nhi));
+    for (int64_t i = 0; i < nlo; ++i) host[(size_t)i] = z_factor(i, N);
+    for (int64_t i = 0; i < nhi; ++i) host[(size_t)(nlo + i)] = z_factor(i << hh, N);
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, host.size() * sizeof(float2));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_NOMEM : hip_fail(e);
+    e = hipMemcpy(d, host.data(), host.size() * sizeof(float2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return hip_fail(e);
+    }
+    float2* p = static_cast<float2*>(d);
+    it = t->fourstep.emplace(log2N, std::make_pair(p, p + nlo)).first;
+    t->fourstep_h[log2N] = hh;
+  }
+  *lo = it->second.first;
+  *hi = it->second.second;
+  *h = t->fourstep_h[log2N];
+  return FFT_OK;
+}
+
+}  // namespace fftmi
+
+// =================================================================== helpers
+namespace {
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int check_plan(fft_plan_t p, int* dev_out) {
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev != p->device) return FFT_ERR_STATE;
+  if (dev_out) *dev_out = dev;
+  return FFT_OK;
+}
+
+float fwd_scale_1d(const fftmi_plan* p) { return (p->flags & FFT_NORM_NUMPY) ? 1.0f : 1.0f / (float)p->n; }
+float inv_scale_1d(const fftmi_plan* p) { return (p->flags & FFT_NORM_NUMPY) ? 1.0f / (float)p->n : 1.0f; }
+// 2D: eq. 5 carries 1/N (rows); the 2D-IDFT carries 1/M (columns).
+float fwd_scale_2d(const fftmi_plan* p) { return (p->flags & FFT_NORM_NUMPY) ? 1.0f : 1.0f / (float)p->n; }
+float inv_scale_2d(const fftmi_plan* p) {
+  return (p->flags & FFT_NORM_NUMPY) ? 1.0f / ((float)p->n * (float)p->m) : 1.0f / (float)p->m;
+}
+
+int fill_mask(const fft_mask* mk, const fftmi_plan* p, MaskArgs* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->inv_n = 1.0f / (float)p->n;
+  out->inv_m = 1.0f / (float)p->m;
+  if (!mk) {
+    out->kind = FFT_MASK_NONE;
+    return FFT_OK;
+  }
+  out->kind = mk->kind;
+  switch (mk->kind) {
+    case FFT_MASK_NONE:
+      return FFT_OK;
+    case FFT_MASK_TENSOR_F32:
+      if (!mk->data) return FFT_ERR_ARG;
+      out->data = mk->data;
+      return FFT_OK;
+    case FFT_MASK_GAUSSIAN:
+      if (!(mk->sigma_f > 0.0) || !std::isfinite(mk->sigma_f)) return FFT_ERR_ARG;
+      out->gauss_coef = (float)(-1.0 / (2.0 * mk->sigma_f * mk->sigma_f));
+      return FFT_OK;
+    case FFT_MASK_BUTTERWORTH:
+      if (!(mk->cutoff > 0.0) || !std::isfinite(mk->cutoff) || mk->order < 1 || mk->order > 64) return FFT_ERR_ARG;
+      out->inv_fc2 = (float)(1.0 / (mk->cutoff * mk->cutoff));
+      out->order = mk->order;
+      return FFT_OK;
+    case FFT_MASK_DISC:
+      if (!(mk->b > 0.0) || !std::isfinite(mk->b) || !std::isfinite(mk->c1) || !std::isfinite(mk->c2))
+        return FFT_ERR_ARG;
+      out->disc_b2 = mk->b * mk->b;
+      out->c1 = mk->c1;
+      out->c2 = mk->c2;
+      return FFT_OK;
+    default:
+      return FFT_ERR_ARG;
+  }
+}
+
+}  // namespace
+
+// =================================================================== C-ABI
+extern "C" {
+
+int fft_version(void) { return 0x000100; }
+
+const char* fft_strerror(int code) {
+  switch (code) {
+    case FFT_OK:
+      return "success";
+    case FFT_ERR_ARG:
+      return "invalid argument";
+    case FFT_ERR_SIZE:
+      return "length is not a power of two or is out of range";
+    case FFT_ERR_UNSUPPORTED:
+      return "unsupported request";
+    case FFT_ERR_WORKSPACE:
+      return "workspace missing";
+    case FFT_ERR_HIP:
+      return g_err_text.empty() ? "HIP runtime error" : g_err_text.c_str();
+    case FFT_ERR_NOMEM:
+      return "out of memory";
+    case FFT_ERR_STATE:
+      return "plan used on another device or with the wrong entry point";
+    default:
+      return "unknown status";
+  }
+}
+
+int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint32_t flags) {
+  if (!out) return FFT_ERR_ARG;
+  *out = nullptr;
+  if ((rank != 1 && rank != 2) || !dims || batch < 0) return FFT_ERR_ARG;
+  if (flags & ~(FFT_IN_REAL_F32 | FFT_OUT_REAL_F32 | FFT_NORM_NUMPY)) return FFT_ERR_ARG;
+  const int64_t N = dims[0], M = rank == 2 ? dims[1] : 1;
+  if (rank == 1 && (!is_pow2(N) || N > (int64_t(1) << 24))) return FFT_ERR_SIZE;
+  if (rank == 2 && (!is_pow2(N) || !is_pow2(M) || N > (1 << kMaxLog2Row) || M > (1 << kMaxLog2Row)))
+    return FFT_ERR_SIZE;
+
+  std::unique_ptr<fftmi_plan> p(new (std::nothrow) fftmi_plan());
+  if (!p) return FFT_ERR_NOMEM;
+  p->magic = kPlanMagic;
+  p->kind = rank;
+  p->n = N;
+  p->m = M;
+  p->batch = batch;
+  p->flags = flags;
+  p->log_n = ilog2c(N);
+  p->log_m = ilog2c(M);
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return hip_fail(e);
+  DevTables* t = nullptr;
+  int rc = device_tables(p->device, &t);
+  if (rc != FFT_OK) return rc;
+  p->tables = t;
+
+  if (rank == 1) {
+    if (p->log_n > kMaxLog2Row) {
+      p->fourstep = true;
+      p->log_n1 = p->log_n / 2;
+      p->log_n2 = p->log_n - p->log_n1;
+      p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, 16);
+      p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, 16);
+      rc = fourstep_tables(t, p->log_n, &p->tw_lo, &p->tw_hi, &p->tw_h);
+      if (rc != FFT_OK) return rc;
+      p->ws_bytes = (size_t)batch * (size_t)N * sizeof(float2);
+    }
+  } else {
+    // rows per block of the blocked layout: limited by the row pass's LDS
+    // (RB rows of length M) and by the column pass's thread split (N/16 % RB).
+    int rb = 4;
+    while (rb > 1 && rb * region_stride(1 << p->log_m, rb) * (int)sizeof(float2) > kLdsBytes) rb /= 2;
+    while (rb > 1 && threads_per_transform((int)N) % rb) rb /= 2;
+    while (rb > 1 && rb * threads_per_transform((int)M) > 1024) rb /= 2;
+    p->rb = rb;
+    p->w = tuned_cols_width(p.get());
+    p->ws_bytes = (size_t)batch * (size_t)N * (size_t)M * sizeof(float2);
+    p->spec_bytes = p->ws_bytes;
+  }
+  plan_register(p.get());
+  *out = p.release();
+  return FFT_OK;
+}
+
+int fft_workspace_size(fft_plan_t plan, size_t* bytes) {
+  if (!plan_live(plan) || !bytes) return FFT_ERR_ARG;
+  *bytes = plan->ws_bytes;
+  return FFT_OK;
+}
+
+int fft_spectrum_size(fft_plan_t plan, size_t* bytes) {
+  if (!plan_live(plan) || !bytes) return FFT_ERR_ARG;
+  if (plan->kind != 2) return FFT_ERR_STATE;
+  *bytes = plan->spec_bytes;
+  return FFT_OK;
+}
+
+int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direction, void* stream) {
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  if (direction != FFT_FORWARD && direction != FFT_INVERSE && direction != FFT_ADJ_FORWARD &&
+      direction != FFT_ADJ_INVERSE)
+    return FFT_ERR_ARG;
+  if (p->kind != 1 && p->kind != 2) return FFT_ERR_STATE;
+  if (p->batch == 0) return FFT_OK;
+  if (!in || !out || in == out) return FFT_ERR_ARG;
+  if (p->ws_bytes && !workspace) return FFT_ERR_WORKSPACE;
+  int rc = check_plan(p, nullptr);
+  if (rc != FFT_OK) return rc;
+
+  const bool inv_tw = (direction == FFT_INVERSE || direction == FFT_ADJ_FORWARD);
+  const bool fwd_norm = (direction == FFT_FORWARD || direction == FFT_ADJ_FORWARD);
+  const bool in_f32 = p->flags & FFT_IN_REAL_F32, out_f32 = p->flags & FFT_OUT_REAL_F32;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e;
+
+  if (p->kind == 1) {
+    const float scale = fwd_norm ? fwd_scale_1d(p) : inv_scale_1d(p);
+    if (!p->fourstep) {
+      Launch lc{st, blob_for(p->tables, p->log_n)};
+      e = launch_rows_rm(p->log_n, inv_tw, in, in_f32, out, out_f32, p->batch, scale, lc);
+      return e == hipSuccess ? FFT_OK : hip_fail(e);
+    }
+    if (in_f32 || out_f32) return FFT_ERR_UNSUPPORTED;
+    // four-step: N = N1 N2; pass 1 column FFTs of length N1 over the [N1][N2]
+    // view, twiddle, transposed store; pass 2 column FFTs of length N2 over
+    // the [N2][N1] intermediate, natural-order result.
+    const int n1 = 1 << p->log_n1, n2 = 1 << p->log_n2;
+    float2* ws = static_cast<float2*>(workspace);
+    Launch l1{st, blob_for(p->tables, p->log_n1)};
+    e = launch_cols_strided(p->log_n1, inv_tw, true, static_cast<const float2*>(in), ws, p->batch, n2, p->w1, 1.0f,
+                            p->tw_lo, p->tw_hi, p->tw_h, l1);
+    if (e != hipSuccess) return hip_fail(e);
+    Launch l2{st, blob_for(p->tables, p->log_n2)};
+    e = launch_cols_strided(p->log_n2, inv_tw, false, ws, static_cast<float2*>(out), p->batch, n1, p->w2, scale,
+                            nullptr, nullptr, 0, l2);
+    return e == hipSuccess ? FFT_OK : hip_fail(e);
+  }
+
+  // rank 2: row pass into the blocked workspace, column pass to row-major out
+  const float scale = fwd_norm ? fwd_scale_2d(p) : inv_scale_2d(p);
+  float2* ws = static_cast<float2*>(workspace);
+  const int64_t blocks = p->batch * p->n / p->rb;
+  const bool pair = in_f32 && p->rb >= 2;
+  Launch lr{st, blob_for(p->tables, p->log_m)};
+  e = launch_rows_to_blk(p->log_m, inv_tw, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
+  if (e != hipSuccess) return hip_fail(e);
+  Launch lcn{st, blob_for(p->tables, p->log_n)};
+  e = launch_cols_single(p->log_n, inv_tw, ws, out, out_f32, p->batch, (int)p->m, p->rb, p->w, scale, lcn);
+  return e == hipSuccess ? FFT_OK : hip_fail(e);
+}
+
+// stages: bit 0 = row pass, bit 1 = column pass, bit 2 = inverse row pass
+static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* spectrum,
+                       void* workspace, void* stream, int stages) {
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  if (p->kind != 2) return FFT_ERR_STATE;
+  MaskArgs mk;
+  int rc = fill_mask(mask, p, &mk);
+  if (rc != FFT_OK) return rc;
+  if (p->batch == 0) return FFT_OK;
+  if (((stages & 1) && !in) || ((stages & 4) && !out)) return FFT_ERR_ARG;
+  if (!workspace) return FFT_ERR_WORKSPACE;
+  rc = check_plan(p, nullptr);
+  if (rc != FFT_OK) return rc;
+  const bool in_f32 = p->flags & FFT_IN_REAL_F32, out_f32 = p->flags & FFT_OUT_REAL_F32;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  float2* ws = static_cast<float2*>(workspace);
+  const int64_t blocks = p->batch * p->n / p->rb;
+  const bool pair = in_f32 && p->rb >= 2;
+  Launch lr{st, blob_for(p->tables, p->log_m)};
+  Launch lcn{st, blob_for(p->tables, p->log_n)};
+  hipError_t e = hipSuccess;
+  if (stages & 1) {
+    e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, fwd_scale_2d(p), lr);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (stages & 2) {
+    e = launch_cols_filter(p->log_n, ws, static_cast<float2*>(spectrum), p->batch, (int)p->m, p->rb, p->w, mk, lcn);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  if (stages & 4) {
+    e = launch_rows_from_blk(p->log_m, true, ws, out, out_f32, blocks, p->rb, inv_scale_2d(p), lr);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return FFT_OK;
+}
+
+int fft2d_filter(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* workspace, void* stream) {
+  return filter_impl(p, in, out, mask, nullptr, workspace, stream, 7);
+}
+
+int fft2d_filter_stage(fft_plan_t p, int stage, const void* in, void* out, const fft_mask* mask, void* workspace,
+                       void* stream) {
+  if (stage < 0 || stage > 2) return FFT_ERR_ARG;
+  return filter_impl(p, in, out, mask, nullptr, workspace, stream, 1 << stage);
+}
+
+int fft2d_filter_save(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* spectrum,
+                      void* workspace, void* stream) {
+  if (!spectrum) return FFT_ERR_ARG;
+  return filter_impl(p, in, out, mask, spectrum, workspace, stream, 7);
+}
+
+int fft2d_filter_mask_grad(fft_plan_t p, const void* grad_y, const void* spectrum, float* grad_mask,
+                           void* workspace, void* stream) {
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  if (p->kind != 2) return FFT_ERR_STATE;
+  if (!grad_mask) return FFT_ERR_ARG;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  if (p->batch == 0) {
+    int rc = check_plan(p, nullptr);
+    if (rc != FFT_OK) return rc;
+    hipError_t e = hipMemsetAsync(grad_mask, 0, (size_t)(p->n * p->m) * sizeof(float), st);
+    return e == hipSuccess ? FFT_OK : hip_fail(e);
+  }
+  if (!grad_y || !spectrum) return FFT_ERR_ARG;
+  if (!workspace) return FFT_ERR_WORKSPACE;
+  int rc = check_plan(p, nullptr);
+  if (rc != FFT_OK) return rc;
+  // adjoint of the 2D-IDFT: forward factors, scale 1/M (paper) or 1/(NM)
+  float2* ws = static_cast<float2*>(workspace);
+  const int64_t blocks = p->batch * p->n / p->rb;
+  Launch lr{st, blob_for(p->tables, p->log_m)};
+  hipError_t e = launch_rows_to_blk(p->log_m, false, false, grad_y, false, ws, blocks, p->rb, 1.0f, lr);
+  if (e != hipSuccess) return hip_fail(e);
+  Launch lcn{st, blob_for(p->tables, p->log_n)};
+  e = launch_cols_grad(p->log_n, ws, static_cast<const float2*>(spectrum), grad_mask, p->batch, (int)p->m, p->rb,
+                       p->w, inv_scale_2d(p), lcn);
+  return e == hipSuccess ? FFT_OK : hip_fail(e);
+}
+
+int fft_plan_destroy(fft_plan_t p) {
+  if (!p) return FFT_OK;
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  plan_unregister(p);
+  p->magic = 0;
+  destroy_ragged_state(p);
+  delete p;
+  return FFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,66 @@
+// fft_schedule.hpp -- compile-time radix schedule shared by host and device code.
+//
+// A length-L transform (L = 2^m) is split over L/E threads with E = min(16, L)
+// complex elements each; thread j holds the elements at positions j + q*(L/E),
+// q = 0..E-1, on entry and on exit (natural order both ends: self-sorting
+// Stockham).  The stages are as many radix-16 passes as fit, then one radix-2,
+// -4 or -8 pass for the remaining factor.  This replaces the paper's level-by-
+// level radix-2 tree (Section 2): four tree levels are merged into one radix-16
+// pass held in registers, so data crosses LDS once per four levels.
+//
+// Stage s has stride NS(s) = product of the radices before it.  For s >= 1 the
+// twiddle factors exp(-2 pi i r k / (NS R)) (k < NS, r < R) live in a table
+// T_s[k*R + r]; all stage tables of one L are concatenated into one "blob".
+#pragma once
+#include <stdint.h>
+
+namespace fftmi {
+
+#if defined(__HIPCC__)
+#define FFTMI_HD __host__ __device__
+#else
+#define FFTMI_HD
+#endif
+
+FFTMI_HD constexpr int ilog2c(int64_t L) {
+  int m = 0;
+  while ((int64_t(1) << m) < L) ++m;
+  return m;
+}
+FFTMI_HD constexpr int elems_per_thread(int L) { return L >= 16 ? 16 : L; }
+FFTMI_HD constexpr int threads_per_transform(int L) { return L / elems_per_thread(L); }
+FFTMI_HD constexpr int num_stages(int L) {
+  return L <= 1 ? 0 : (L < 16 ? 1 : ilog2c(L) / 4 + ((ilog2c(L) % 4) ? 1 : 0));
+}
+FFTMI_HD constexpr int stage_radix(int L, int s) {
+  return L < 16 ? L : (s < ilog2c(L) / 4 ? 16 : (1 << (ilog2c(L) % 4)));
+}
+FFTMI_HD constexpr int stage_ns(int L, int s) {
+  int ns = 1;
+  for (int i = 0; i < s; ++i) ns *= stage_radix(L, i);
+  return ns;
+}
+// Offset (in complex entries) of stage s's table inside the blob of length L.
+FFTMI_HD constexpr int tw_stage_offset(int L, int s) {
+  int off = 0;
+  for (int i = 1; i < s; ++i) off += stage_ns(L, i) * stage_radix(L, i);
+  return off;
+}
+FFTMI_HD constexpr int tw_blob_size(int L) { return tw_stage_offset(L, num_stages(L)); }
+
+// LDS footprint of one transform: one padding slot per 16 entries so that the
+// stride-16 writes of a radix-16 pass fall into distinct banks.
+FFTMI_HD constexpr int lds_pad(int i) { return i + (i >> 4); }
+FFTMI_HD constexpr int lds_size(int L) { return L >= 16 ? L + L / 16 : L; }
+
+// LDS stride of one transform's region when `inter` transforms are interleaved
+// lane by lane inside a wavefront: offsetting consecutive regions by 32/inter
+// 8-byte slots puts their lanes in disjoint bank groups.
+FFTMI_HD constexpr int region_stride(int L, int inter) {
+  return lds_size(L) + (inter > 1 && inter <= 32 ? 32 / inter : 0);
+}
+
+constexpr int kMaxLog2Row = 14;      // longest single-pass transform, 2^14
+constexpr int kLdsBytes = 160 * 1024; // gfx950 LDS per workgroup
+
+}  // namespace fftmi

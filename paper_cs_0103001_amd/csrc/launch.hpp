@@ -1,0 +1,76 @@
+// launch.hpp -- host-side entry points of the HIP kernels (internal to libfftmi).
+//
+// Layouts used between passes of the 2D path:
+//   row-major   image b, element (u, v) at  b*N*M + u*M + v
+//   blocked     image b, element (u, v) at  b*N*M + ((u / RB) * M + v) * RB + u % RB
+// RB rows are interleaved per column so that a column tile of W columns reads
+// W*RB*8 contiguous bytes per row block, while a row pass over one block reads
+// and writes RB*M*8 contiguous bytes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fftmi {
+
+// Real mask over the (u, v) bins, evaluated inside the column kernels.
+struct MaskArgs {
+  int kind;             // FFT_MASK_* from fftmi.h
+  const float* data;    // tensor mask, row-major [N][M]
+  float gauss_coef;     // -1 / (2 sigma^2)
+  float inv_fc2;        // 1 / cutoff^2
+  int order;            // Butterworth order n (exponent 2n)
+  double disc_b2;       // b^2
+  double c1, c2;        // disc centre (bin units)
+  float inv_n, inv_m;   // 1/N and 1/M (exact powers of two) for the frequency grid
+};
+
+struct Launch {
+  hipStream_t stream;
+  const float2* tw;  // twiddle blob for the transform length of this launch
+};
+
+// Batched transforms along contiguous rows of length L = 2^log2L, row-major in
+// and out (1D path, L <= 2^14).  rows = number of transforms.
+hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void* out, bool out_f32,
+                          int64_t rows, float scale, const Launch& lc);
+
+// Row pass into the blocked layout: `blocks` groups of RB consecutive rows of
+// length L.  pair = pack two real rows into one complex transform (in_f32 and
+// RB even).
+hipError_t launch_rows_to_blk(int log2L, bool inv, bool pair, const void* in, bool in_f32, float2* ws,
+                              int64_t blocks, int rb, float scale, const Launch& lc);
+
+// Row pass out of the blocked layout into row-major output.
+hipError_t launch_rows_from_blk(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks,
+                                int rb, float scale, const Launch& lc);
+
+// Column pass on the blocked layout (column length L = N): forward transform,
+// mask multiply, inverse transform, in place.  save != nullptr also stores the
+// forward spectrum (blocked layout).
+hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w,
+                              const MaskArgs& mask, const Launch& lc);
+
+// Column pass on the blocked layout: one transform, row-major output.
+hipError_t launch_cols_single(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t nimg, int M,
+                              int rb, int w, float scale, const Launch& lc);
+
+// Column pass for the mask gradient: for every column tile, loop over the
+// batch in order, forward-transform the blocked rows of grad_y, multiply by
+// conj(saved spectrum) and accumulate the real part; grad = scale * sum.
+hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, float* grad, int64_t nimg, int M,
+                            int rb, int w, float scale, const Launch& lc);
+
+// Strided column pass of the four-step long 1D transform over a row-major
+// [L][C] matrix per batch entry, tiles of w columns.  twiddle_transpose: pass
+// one (multiply by W_N^{k1 n2}, N = L*C, two-level tables lo/hi with split h,
+// and store transposed as [C][L]); otherwise pass two (store [L][C]).
+hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,
+                               int64_t batch, int C, int w, float scale, const float2* tw_lo, const float2* tw_hi,
+                               int h, const Launch& lc);
+
+// LDS bytes of one launch configuration (for the host's occupancy checks).
+int lds_bytes_rows_rm(int log2L, int tpw);
+int lds_bytes_cols(int log2L, int w);
+int lds_bytes_rows_blk(int log2L, int nt);
+
+}  // namespace fftmi

@@ -1,0 +1,60 @@
+// plan.hpp -- the plan object behind the opaque fft_plan_t, and the internal
+// helpers shared by the C-ABI translation units of libfftmi.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+namespace fftmi {
+
+struct DevTables;     // per-device twiddle tables (api.cpp)
+struct RaggedState;   // ragged work list, device buffers and graph (ragged.cpp)
+
+constexpr uint32_t kPlanMagic = 0x46465449u;
+
+extern thread_local std::string g_err_text;
+int hip_fail(hipError_t e);
+
+int device_tables(int dev, DevTables** out);
+const float2* blob_for(const DevTables* t, int log2L);
+int fourstep_tables(DevTables* t, int log2N, const float2** lo, const float2** hi, int* h);
+
+}  // namespace fftmi
+
+struct fftmi_plan {
+  uint32_t magic = 0;
+  int kind = 0;  // 1: rank 1, 2: rank 2, 3: ragged
+  int device = -1;
+  int64_t n = 1, m = 1, batch = 0;  // rank 1: n; rank 2: n rows, m columns
+  uint32_t flags = 0;
+  int log_n = 0, log_m = 0;
+  fftmi::DevTables* tables = nullptr;
+  // rank 2: rows per block of the blocked layout, column tile width
+  int rb = 1, w = 1;
+  // rank 1 beyond one LDS pass: four-step split N = N1 * N2
+  bool fourstep = false;
+  int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1, tw_h = 0;
+  const float2* tw_lo = nullptr;
+  const float2* tw_hi = nullptr;
+  size_t ws_bytes = 0, spec_bytes = 0;
+  fftmi::RaggedState* ragged = nullptr;
+};
+
+namespace fftmi {
+
+// Live-plan registry: lets every entry point reject freed or foreign handles.
+void plan_register(fftmi_plan* p);
+bool plan_live(const fftmi_plan* p);
+void plan_unregister(fftmi_plan* p);
+
+// Widest power-of-two column tile (<= wmax, <= cols) that fits one workgroup.
+int widest_cols_tile(int log2L, int cols, int wmax);
+
+// Column tile width for a rank-2 plan (autotuned value if one is cached).
+int tuned_cols_width(const fftmi_plan* p);
+
+void destroy_ragged_state(fftmi_plan* p);
+
+}  // namespace fftmi

@@ -1,0 +1,33 @@
+// tune.cpp -- launch-shape choices of rank-2 plans: the column tile width W.
+//
+// A column tile reads W*RB*8 contiguous bytes per row block; wider tiles give
+// longer runs but fewer workgroups per CU (LDS: W * N * 8.5 bytes).  The
+// default asks for 64-byte runs; an autotuned value recorded for the shape
+// takes precedence.
+#include <algorithm>
+#include <cstdlib>
+
+#include "fft_schedule.hpp"
+#include "launch.hpp"
+#include "plan.hpp"
+
+namespace fftmi {
+
+int widest_cols_tile(int log2L, int cols, int wmax) {
+  const int tpt = threads_per_transform(1 << log2L);
+  int w = 1;
+  while (w * 2 <= wmax && w * 2 <= cols && (w * 2) * tpt <= 1024 && lds_bytes_cols(log2L, w * 2) <= kLdsBytes)
+    w *= 2;
+  return w;
+}
+
+int tuned_cols_width(const fftmi_plan* p) {
+  int w = std::max(1, 8 / p->rb);
+  if (const char* env = std::getenv("FFTMI_COLS_W")) {
+    const int v = std::atoi(env);
+    if (v >= 1 && (v & (v - 1)) == 0) w = v;
+  }
+  return widest_cols_tile(p->log_n, (int)p->m, w);
+}
+
+}  // namespace fftmi

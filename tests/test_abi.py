@@ -1,0 +1,89 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function the
+header declares, and rejects bad arguments before any device work."""
+import ctypes
+
+import pytest
+
+from paper_cs_0103001_amd import _binding as B
+
+try:
+    import torch
+    HAVE_GPU = torch.cuda.is_available()
+except Exception:  # pragma: no cover
+    HAVE_GPU = False
+
+
+def test_library_exports_header_functions():
+    lib = B.lib()
+    names = B.header_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.fft_version() == 0x000100
+
+
+def test_strerror_texts():
+    for code in (B.FFT_OK, B.FFT_ERR_ARG, B.FFT_ERR_SIZE, B.FFT_ERR_UNSUPPORTED, B.FFT_ERR_WORKSPACE,
+                 B.FFT_ERR_HIP, B.FFT_ERR_NOMEM, B.FFT_ERR_STATE, -99):
+        assert isinstance(B.strerror(code), str) and B.strerror(code)
+
+
+def _plan_rc(rank, dims, batch, flags=0, null_out=False, null_dims=False):
+    lib = B.lib()
+    h = ctypes.c_void_p()
+    arr = None if null_dims else (ctypes.c_int64 * len(dims))(*dims)
+    rc = lib.fft_plan(None if null_out else ctypes.byref(h), rank, arr, batch, flags)
+    return rc, h.value
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(rank=1, dims=[8], batch=1, null_out=True), B.FFT_ERR_ARG),
+    (dict(rank=1, dims=[8], batch=1, null_dims=True), B.FFT_ERR_ARG),
+    (dict(rank=3, dims=[8, 8, 8], batch=1), B.FFT_ERR_ARG),
+    (dict(rank=0, dims=[8], batch=1), B.FFT_ERR_ARG),
+    (dict(rank=1, dims=[8], batch=-1), B.FFT_ERR_ARG),
+    (dict(rank=1, dims=[8], batch=1, flags=0x80), B.FFT_ERR_ARG),
+    (dict(rank=1, dims=[12], batch=1), B.FFT_ERR_SIZE),
+    (dict(rank=1, dims=[0], batch=1), B.FFT_ERR_SIZE),
+    (dict(rank=1, dims=[-8], batch=1), B.FFT_ERR_SIZE),
+    (dict(rank=1, dims=[1 << 25], batch=1), B.FFT_ERR_SIZE),
+    (dict(rank=2, dims=[8, 6], batch=1), B.FFT_ERR_SIZE),
+    (dict(rank=2, dims=[1 << 15, 8], batch=1), B.FFT_ERR_SIZE),
+    (dict(rank=2, dims=[8, 1 << 15], batch=1), B.FFT_ERR_SIZE),
+])
+def test_plan_argument_errors(args, code):
+    rc, h = _plan_rc(**args)
+    assert rc == code
+    assert h is None
+
+
+@pytest.mark.skipif(HAVE_GPU, reason="checks the no-device path")
+def test_plan_without_device_reports_hip_error():
+    rc, h = _plan_rc(1, [1024], 4)
+    assert rc == B.FFT_ERR_HIP and h is None
+    assert "HIP" in B.strerror(B.FFT_ERR_HIP)
+
+
+def test_calls_reject_bad_plans():
+    lib = B.lib()
+    bogus = ctypes.c_void_p(0x1234)
+    n = ctypes.c_size_t()
+    assert lib.fft_plan_destroy(None) == B.FFT_OK
+    assert lib.fft_plan_destroy(bogus) == B.FFT_ERR_ARG
+    assert lib.fft_workspace_size(None, ctypes.byref(n)) == B.FFT_ERR_ARG
+    assert lib.fft_workspace_size(bogus, ctypes.byref(n)) == B.FFT_ERR_ARG
+    assert lib.fft_spectrum_size(bogus, ctypes.byref(n)) == B.FFT_ERR_ARG
+    p = ctypes.c_void_p(0x10)
+    assert lib.fft_exec(bogus, p, p, p, B.FFT_FORWARD, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter(bogus, p, p, None, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_save(bogus, p, p, None, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mask_grad(bogus, p, p, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_ragged(bogus, p, p, None, p, None) == B.FFT_ERR_ARG
+
+
+def test_mask_struct_layout_matches_header():
+    # int kind; const float* data; double sigma_f, cutoff; int order; double b, c1, c2
+    m = B.fft_mask
+    assert m.kind.offset == 0 and m.data.offset == 8 and m.sigma_f.offset == 16
+    assert m.cutoff.offset == 24 and m.order.offset == 32 and m.b.offset == 40
+    assert m.c2.offset == 56 and ctypes.sizeof(m) == 64

@@ -1,0 +1,129 @@
+"""Learnable-mask filter: GPU gradients against the FP64 oracle's analytic
+gradient, a GPU directional finite difference (eps = 1e-3, loss summed in
+FP64) and the adjoint dot-product identity."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, announce, need_gpu, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _loss(y, clean):
+    # mean over the real and imaginary parts of |y - clean|^2, K = B N M
+    d = y - clean.to(y.dtype)
+    return (d.real.square() + d.imag.square()).sum() / clean.numel()
+
+
+def _pairs(B, N, M):
+    noisy, clean = zip(*[synth.learn_pair(b, N, M) for b in range(B)])
+    return np.stack(noisy), np.stack(clean)
+
+
+@pytest.mark.parametrize("B,N,M", [(2, 64, 64), (3, 32, 128), (2, 128, 32), (8, 1024, 1024)])
+def test_mask_gradient_vs_oracle(B, N, M):
+    import torch
+    from paper_cs_0103001_amd.autograd import fft_filter
+    noisy, clean = _pairs(B, N, M)
+    rng = np.random.default_rng(B * N + M)
+    mask = rng.uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    m = to_dev(mask).requires_grad_(True)
+    announce("mask grad B=%d %dx%d" % (B, N, M))
+    y = fft_filter(to_dev(noisy), m)
+    L = _loss(y, to_dev(clean))
+    L.backward()
+    g = to_host(m.grad)
+    y_ref, L_ref, g_ref = oracle.loss_grad(noisy, clean, mask)
+    assert rel_l2(to_host(y), y_ref, 2) < TOL
+    assert abs(float(L) - L_ref) / L_ref < 1e-5
+    err = rel_l2(g, g_ref, 2)
+    print("grad relL2 = %.3e" % err)
+    assert err < TOL
+    del torch
+
+
+@pytest.mark.xfail(strict=True, reason="generic autograd route: at mask = 1 the residual y - clean is the "
+                   "noise alone, and the float32 round-trip error of y (relative 1e-7 per spectral bin, "
+                   "weighted by |X|) reaches 2e-4 of the gradient; the fused filter+MSE op is the stable route")
+def test_mask_gradient_at_mask_one_learn_workload_subset():
+    """mask = 1 (the learnable workload's initial value): y = noisy, gradient
+    against the oracle, 1024x1024 images, batch 4 of the batch-64 workload."""
+    import torch
+    from paper_cs_0103001_amd.autograd import fft_filter
+    noisy, clean = _pairs(4, 1024, 1024)
+    m = torch.ones((1024, 1024), dtype=torch.float32, device="cuda", requires_grad=True)
+    announce("mask grad at ones")
+    y = fft_filter(to_dev(noisy), m)
+    _loss(y, to_dev(clean)).backward()
+    _, _, g_ref = oracle.loss_grad(noisy, clean, np.ones((1024, 1024)))
+    assert rel_l2(to_host(y), noisy.astype(np.complex128), 2) < TOL
+    assert rel_l2(to_host(m.grad), g_ref, 2) < TOL
+
+
+def test_directional_finite_difference():
+    import torch
+    from paper_cs_0103001_amd.autograd import fft_filter
+    B, N, M = 4, 256, 256
+    noisy, clean = _pairs(B, N, M)
+    xd, cd = to_dev(noisy), to_dev(clean)
+    rng = np.random.default_rng(7)
+    mask = rng.uniform(0.5, 1.0, (N, M)).astype(np.float32)
+    d = rng.choice([-1.0, 1.0], (N, M)).astype(np.float32)
+    m = to_dev(mask).requires_grad_(True)
+    _loss(fft_filter(xd, m), cd).backward()
+    gd = float((m.grad.double() * to_dev(d).double()).sum())
+    eps = 1e-3
+
+    def L64(mm):
+        with torch.no_grad():
+            y = fft_filter(xd, mm).to(torch.complex128)
+            dd = y - cd.double()
+            return float((dd.real.square() + dd.imag.square()).sum() / cd.numel())
+    announce("directional FD")
+    fd = (L64(to_dev(mask + eps * d)) - L64(to_dev(mask - eps * d))) / (2 * eps)
+    print("FD %.6e  grad.d %.6e" % (fd, gd))
+    # the loss is quadratic in the mask, so the central difference is exact up
+    # to the float32 rounding of y (about 1e-7 relative per element)
+    assert abs(fd - gd) <= 2e-2 * abs(gd)
+
+
+def test_adjoint_dot_product():
+    """<FWD2 x, y> = <x, FWD2^H y> with FWD2^H = ADJ_FORWARD, for random complex x, y."""
+    import torch
+    from paper_cs_0103001_amd import api
+    from paper_cs_0103001_amd import _binding as Bn
+    for (N, M) in [(64, 64), (32, 128)]:
+        x = synth.uniform_complex((N, M), (61, N))
+        y = synth.uniform_complex((N, M), (62, N))
+        Fx = to_host(api.fft2(to_dev(x))).astype(np.complex128)
+        Ahy = to_host(api.transform(to_dev(y), 2, Bn.FFT_ADJ_FORWARD)).astype(np.complex128)
+        lhs = np.vdot(y.astype(np.complex128), Fx)
+        rhs = np.vdot(Ahy, x.astype(np.complex128))
+        assert abs(lhs - rhs) < 1e-5 * abs(lhs)
+        Gy = to_host(api.ifft2(to_dev(y))).astype(np.complex128)
+        Ahx = to_host(api.transform(to_dev(x), 2, Bn.FFT_ADJ_INVERSE)).astype(np.complex128)
+        assert abs(np.vdot(x.astype(np.complex128), Gy) - np.vdot(Ahx, y.astype(np.complex128))) < 1e-5 * abs(
+            np.vdot(x.astype(np.complex128), Gy))
+    del torch
+
+
+def test_input_gradient_is_filter_of_upstream_gradient():
+    import torch
+    from paper_cs_0103001_amd.autograd import fft_filter
+    N = M = 64
+    noisy, clean = _pairs(2, N, M)
+    mask = np.random.default_rng(3).uniform(0, 1, (N, M)).astype(np.float32)
+    x = to_dev(noisy).requires_grad_(True)
+    _loss(fft_filter(x, to_dev(mask)), to_dev(clean)).backward()
+    # d/dx of mean|y - c|^2 for real x: Re(filter(2 (y - c) / K)); the filter is self-adjoint
+    y_ref, _, _ = oracle.loss_grad(noisy, clean, mask)
+    g_ref = oracle.filter2(2.0 * (y_ref - clean) / clean.size, mask).real
+    assert rel_l2(to_host(x.grad), g_ref, 2) < TOL
+    del torch
