@@ -40,6 +40,7 @@ static float2 z_factor(int64_t t, int64_t n) {
 struct DevTables {
   float2* blob = nullptr;
   int64_t off[kMaxLog2Row + 1] = {};
+  int64_t off_lds[kMaxLog2Row + 1] = {};  // LDS-layout copies, after the global-layout tables
   std::map<int, std::pair<float2*, float2*>> fourstep;  // log2 N -> (lo, hi)
   std::map<int, int> fourstep_h;
 };
@@ -62,6 +63,17 @@ int build_blobs(DevTables* t) {
         for (int q = 0; q < r; ++q) host.push_back(z_factor((int64_t)q * k, (int64_t)ns * r));
     }
     while (host.size() % 32) host.push_back(make_float2(0.f, 0.f));  // 256-byte aligned starts
+  }
+  // the same factors in the layout the persistent kernels copy to LDS
+  for (int lg = 0; lg <= kMaxLog2Row; ++lg) {
+    const int L = 1 << lg;
+    t->off_lds[lg] = (int64_t)host.size();
+    for (int s = 1; s < num_stages(L); ++s) {
+      const int ns = stage_ns(L, s), r = stage_radix(L, s);
+      for (int q = 1; q < r; ++q)
+        for (int k = 0; k < ns; ++k) host.push_back(z_factor((int64_t)q * k, (int64_t)ns * r));
+    }
+    while (host.size() % 32) host.push_back(make_float2(0.f, 0.f));
   }
   void* d = nullptr;
   hipError_t e = hipMalloc(&d, host.size() * sizeof(float2));
@@ -98,6 +110,11 @@ int device_tables(int dev, DevTables** out) {
 }
 
 const float2* blob_for(const DevTables* t, int log2L) { return t->blob + t->off[log2L]; }
+const float2* lds_blob_for(const DevTables* t, int log2L) { return t->blob + t->off_lds[log2L]; }
+
+Launch launch_for(hipStream_t st, const DevTables* t, int log2L) {
+  return Launch{st, blob_for(t, log2L), lds_blob_for(t, log2L)};
+}
 
 void plan_register(fftmi_plan* p) {
   std::lock_guard<std::mutex> lk(g_plan_mu);
@@ -272,12 +289,10 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       p->ws_bytes = (size_t)batch * (size_t)N * sizeof(float2);
     }
   } else {
-    // rows per block of the blocked layout: limited by the row pass's LDS
-    // (RB rows of length M) and by the column pass's thread split (N/16 % RB).
+    // rows per block of the blocked layout: limited by the column pass's
+    // thread split (N/16 % RB); the row passes take whole or half blocks.
     int rb = 4;
-    while (rb > 1 && rb * region_stride(1 << p->log_m, rb) * (int)sizeof(float2) > kLdsBytes) rb /= 2;
     while (rb > 1 && threads_per_transform((int)N) % rb) rb /= 2;
-    while (rb > 1 && rb * threads_per_transform((int)M) > 1024) rb /= 2;
     p->rb = rb;
     p->w = tuned_cols_width(p.get());
     p->ws_bytes = (size_t)batch * (size_t)N * (size_t)M * sizeof(float2);
@@ -322,7 +337,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
   if (p->kind == 1) {
     const float scale = fwd_norm ? fwd_scale_1d(p) : inv_scale_1d(p);
     if (!p->fourstep) {
-      Launch lc{st, blob_for(p->tables, p->log_n)};
+      Launch lc = launch_for(st, p->tables, p->log_n);
       e = launch_rows_rm(p->log_n, inv_tw, in, in_f32, out, out_f32, p->batch, scale, lc);
       return e == hipSuccess ? FFT_OK : hip_fail(e);
     }
@@ -332,11 +347,11 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
     // the [N2][N1] intermediate, natural-order result.
     const int n1 = 1 << p->log_n1, n2 = 1 << p->log_n2;
     float2* ws = static_cast<float2*>(workspace);
-    Launch l1{st, blob_for(p->tables, p->log_n1)};
+    Launch l1 = launch_for(st, p->tables, p->log_n1);
     e = launch_cols_strided(p->log_n1, inv_tw, true, static_cast<const float2*>(in), ws, p->batch, n2, p->w1, 1.0f,
                             p->tw_lo, p->tw_hi, p->tw_h, l1);
     if (e != hipSuccess) return hip_fail(e);
-    Launch l2{st, blob_for(p->tables, p->log_n2)};
+    Launch l2 = launch_for(st, p->tables, p->log_n2);
     e = launch_cols_strided(p->log_n2, inv_tw, false, ws, static_cast<float2*>(out), p->batch, n1, p->w2, scale,
                             nullptr, nullptr, 0, l2);
     return e == hipSuccess ? FFT_OK : hip_fail(e);
@@ -347,10 +362,10 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
   float2* ws = static_cast<float2*>(workspace);
   const int64_t blocks = p->batch * p->n / p->rb;
   const bool pair = in_f32 && p->rb >= 2;
-  Launch lr{st, blob_for(p->tables, p->log_m)};
+  Launch lr = launch_for(st, p->tables, p->log_m);
   e = launch_rows_to_blk(p->log_m, inv_tw, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
-  Launch lcn{st, blob_for(p->tables, p->log_n)};
+  Launch lcn = launch_for(st, p->tables, p->log_n);
   e = launch_cols_single(p->log_n, inv_tw, ws, out, out_f32, p->batch, (int)p->m, p->rb, p->w, scale, lcn);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
@@ -373,8 +388,8 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   float2* ws = static_cast<float2*>(workspace);
   const int64_t blocks = p->batch * p->n / p->rb;
   const bool pair = in_f32 && p->rb >= 2;
-  Launch lr{st, blob_for(p->tables, p->log_m)};
-  Launch lcn{st, blob_for(p->tables, p->log_n)};
+  Launch lr = launch_for(st, p->tables, p->log_m);
+  Launch lcn = launch_for(st, p->tables, p->log_n);
   hipError_t e = hipSuccess;
   if (stages & 1) {
     e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, fwd_scale_2d(p), lr);
@@ -426,10 +441,10 @@ int fft2d_filter_mask_grad(fft_plan_t p, const void* grad_y, const void* spectru
   // adjoint of the 2D-IDFT: forward factors, scale 1/M (paper) or 1/(NM)
   float2* ws = static_cast<float2*>(workspace);
   const int64_t blocks = p->batch * p->n / p->rb;
-  Launch lr{st, blob_for(p->tables, p->log_m)};
+  Launch lr = launch_for(st, p->tables, p->log_m);
   hipError_t e = launch_rows_to_blk(p->log_m, false, false, grad_y, false, ws, blocks, p->rb, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
-  Launch lcn{st, blob_for(p->tables, p->log_n)};
+  Launch lcn = launch_for(st, p->tables, p->log_n);
   e = launch_cols_grad(p->log_n, ws, static_cast<const float2*>(spectrum), grad_mask, p->batch, (int)p->m, p->rb,
                        p->w, inv_scale_2d(p), lcn);
   return e == hipSuccess ? FFT_OK : hip_fail(e);

@@ -13,6 +13,7 @@
 #define FFTMI_TW_PREFETCH 0
 #endif
 
+
 namespace fftmi {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -182,6 +183,28 @@ __device__ __forceinline__ void stage_twiddles(float2* tw_reg, int j, const floa
   }
 }
 
+// The same from the LDS copy of the tables (layout of lds_tw_offset).
+template <int L, int S>
+__device__ __forceinline__ void stage_twiddles_lds(float2* tw_reg, int j, const float2* twl) {
+  using I = StageInfo<L, S>;
+  if constexpr (I::NS > 1) {
+    const float2* base = twl + lds_tw_offset(L, S);
+#pragma unroll
+    for (int s = 0; s < I::BPT; ++s) {
+      const int k = (j + s * I::TPT) & (I::NS - 1);
+#pragma unroll
+      for (int r = 1; r < I::R; ++r) tw_reg[s * (I::R - 1) + r - 1] = base[(r - 1) * I::NS + k];
+    }
+  }
+}
+
+// Copy the LDS-layout twiddles of length L into LDS (all threads of the
+// workgroup; the first exchange's barriers order it before any use).
+template <int L>
+__device__ __forceinline__ void load_twiddles_lds(float2* twl, const float2* __restrict__ src, int tid, int nthr) {
+  for (int i = tid; i < lds_tw_entries(L); i += nthr) twl[i] = __ldg(src + i);
+}
+
 template <int L, int S, bool INV>
 __device__ __forceinline__ void stage_compute(float2 (&a)[elems_per_thread(L)], const float2* tw_reg) {
   using I = StageInfo<L, S>;
@@ -200,69 +223,170 @@ __device__ __forceinline__ void stage_compute(float2 (&a)[elems_per_thread(L)], 
   }
 }
 
-template <int L, int S>
-__device__ __forceinline__ void stage_store(const float2 (&a)[elems_per_thread(L)], int j, float2* x) {
+// Workgroup barrier for LDS exchanges.  __syncthreads() also waits for every
+// outstanding global load and store of the wave (a workgroup fence), which
+// would stall on the next tile's prefetch; the exchanges only need LDS
+// accesses ordered: wait for this wave's LDS operations, then meet at the
+// barrier.  The memory clobber keeps the compiler from moving LDS accesses
+// across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// LDS parts: the real and the imaginary halves of a complex value go through
+// LDS separately when FFTMI_SPLIT_X is set (4-byte entries, half the LDS per
+// transform, twice the barriers); otherwise whole complex values (8 bytes).
+enum { kRe = 0, kIm = 1, kBoth = 2 };
+
+template <int PART>
+__device__ __forceinline__ void lds_put(void* x, int i, float2 v) {
+  if constexpr (PART == kBoth)
+    static_cast<float2*>(x)[i] = v;
+  else
+    static_cast<float*>(x)[i] = PART == kRe ? v.x : v.y;
+}
+
+template <int PART>
+__device__ __forceinline__ void lds_get(const void* x, int i, float2& v) {
+  if constexpr (PART == kBoth)
+    v = static_cast<const float2*>(x)[i];
+  else if constexpr (PART == kRe)
+    v.x = static_cast<const float*>(x)[i];
+  else
+    v.y = static_cast<const float*>(x)[i];
+}
+
+// Padded LDS positions are written as pad(base) + pad(offset) with a
+// compile-time offset, which the hardware takes as an instruction immediate.
+// This is exact when the offset is a multiple of 16, or when base is a
+// multiple of 16 and the offset is below 16, or (natural positions
+// j + q*TPT, j < TPT, TPT a power of two) when base % 16 + offset % 16 < 16.
+template <int L, int S, int PART>
+__device__ __forceinline__ void stage_store(const float2 (&a)[elems_per_thread(L)], int j, void* x) {
   using I = StageInfo<L, S>;
+  static_assert(I::NS % 16 == 0 || (I::NS == 1 && I::R == 16), "padded offsets must split exactly");
 #pragma unroll
   for (int s = 0; s < I::BPT; ++s) {
     const int b = j + s * I::TPT;
-    const int base = (b & ~(I::NS - 1)) * I::R + (b & (I::NS - 1));
+    const int pb = lds_pad((b & ~(I::NS - 1)) * I::R + (b & (I::NS - 1)));
 #pragma unroll
-    for (int r = 0; r < I::R; ++r) x[lds_pad(base + r * I::NS)] = a[s + r * I::BPT];
+    for (int r = 0; r < I::R; ++r) lds_put<PART>(x, pb + lds_pad(r * I::NS), a[s + r * I::BPT]);
   }
 }
 
-template <int L>
-__device__ __forceinline__ void gather_natural(float2 (&a)[elems_per_thread(L)], int j, const float2* x) {
+template <int L, int PART>
+__device__ __forceinline__ void gather_natural(float2 (&a)[elems_per_thread(L)], int j, const void* x) {
   constexpr int E = elems_per_thread(L), TPT = L / E;
+  const int pj = lds_pad(j);
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = x[lds_pad(j + q * TPT)];
+  for (int q = 0; q < E; ++q) lds_get<PART>(x, pj + lds_pad(q * TPT), a[q]);
 }
 
-template <int L>
-__device__ __forceinline__ void scatter_natural(const float2 (&a)[elems_per_thread(L)], int j, float2* x) {
+template <int L, int PART>
+__device__ __forceinline__ void scatter_natural(const float2 (&a)[elems_per_thread(L)], int j, void* x) {
   constexpr int E = elems_per_thread(L), TPT = L / E;
+  const int pj = lds_pad(j);
 #pragma unroll
-  for (int q = 0; q < E; ++q) x[lds_pad(j + q * TPT)] = a[q];
+  for (int q = 0; q < E; ++q) lds_put<PART>(x, pj + lds_pad(q * TPT), a[q]);
 }
 
-template <int L, int S, bool INV>
+// Stage S-1 outputs -> LDS -> stage S inputs (natural positions j + q*TPT).
+template <int L, int S>
+__device__ __forceinline__ void exchange(float2 (&a)[elems_per_thread(L)], int j, void* x) {
+  if constexpr (kSplitExchange) {
+    lds_barrier();  // earlier readers of x are done
+    stage_store<L, S - 1, kRe>(a, j, x);
+    lds_barrier();
+    gather_natural<L, kRe>(a, j, x);
+    lds_barrier();
+    stage_store<L, S - 1, kIm>(a, j, x);
+    lds_barrier();
+    gather_natural<L, kIm>(a, j, x);
+  } else {
+    lds_barrier();
+    stage_store<L, S - 1, kBoth>(a, j, x);
+    lds_barrier();
+    gather_natural<L, kBoth>(a, j, x);
+  }
+}
+
+// Where a transform's twiddle factors come from.
+enum TwMode {
+  kTwGlobal = 0,  // loaded from the global tables at every stage
+  kTwLds = 1,     // loaded from an LDS copy of the tables
+  kTwReg = 2,     // held in registers for the kernel's whole run
+};
+
+// Register-held twiddles: all stages s >= 1 of one thread, in stage order.
+template <int L>
+__host__ __device__ constexpr int reg_tw_offset(int s) {
+  int off = 0;
+  for (int i = 1; i < s; ++i) {
+    const int ns = stage_ns(L, i), r = stage_radix(L, i);
+    off += ns > 1 ? (elems_per_thread(L) / r) * (r - 1) : 0;
+  }
+  return off;
+}
+template <int L>
+__host__ __device__ constexpr int reg_tw_count() {
+  return reg_tw_offset<L>(num_stages(L)) > 0 ? reg_tw_offset<L>(num_stages(L)) : 1;
+}
+
+// Load thread j's twiddles of every stage from the global tables once.
+template <int L, int S = 1>
+__device__ __forceinline__ void load_twiddles_reg(float2 (&twr)[reg_tw_count<L>()], int j,
+                                                  const float2* __restrict__ blob) {
+  if constexpr (S < num_stages(L)) {
+    stage_twiddles<L, S>(twr + reg_tw_offset<L>(S), j, blob);
+    load_twiddles_reg<L, S + 1>(twr, j, blob);
+  }
+}
+
+template <int L, int S, bool INV, int TWM>
 struct StageChain {
-  __device__ __forceinline__ static void run(float2 (&a)[elems_per_thread(L)], int j, float2* x,
-                                             const float2* __restrict__ blob) {
+  __device__ __forceinline__ static void run(float2 (&a)[elems_per_thread(L)], int j, void* x,
+                                             const float2* __restrict__ tws) {
     if constexpr (S < num_stages(L)) {
-      float2 tw[StageInfo<L, S>::NTW > 0 ? StageInfo<L, S>::NTW : 1];
-#if FFTMI_TW_PREFETCH
-      stage_twiddles<L, S>(tw, j, blob);
-#endif
-      __syncthreads();  // earlier readers of x are done
-      stage_store<L, S - 1>(a, j, x);
-      __syncthreads();
-      gather_natural<L>(a, j, x);
-#if !FFTMI_TW_PREFETCH
-      stage_twiddles<L, S>(tw, j, blob);
-#endif
-      stage_compute<L, S, INV>(a, tw);
-      StageChain<L, S + 1, INV>::run(a, j, x, blob);
+      if constexpr (TWM == kTwReg) {
+        exchange<L, S>(a, j, x);
+        stage_compute<L, S, INV>(a, tws + reg_tw_offset<L>(S));
+      } else {
+        float2 tw[StageInfo<L, S>::NTW > 0 ? StageInfo<L, S>::NTW : 1];
+        if constexpr (TWM == kTwLds) {
+          exchange<L, S>(a, j, x);
+          stage_twiddles_lds<L, S>(tw, j, tws);
+        } else {
+          if constexpr (FFTMI_TW_PREFETCH) stage_twiddles<L, S>(tw, j, tws);
+          exchange<L, S>(a, j, x);
+          if constexpr (!FFTMI_TW_PREFETCH) stage_twiddles<L, S>(tw, j, tws);
+        }
+        stage_compute<L, S, INV>(a, tw);
+      }
+      StageChain<L, S + 1, INV, TWM>::run(a, j, x, tws);
     }
   }
 };
 
 // Whole transform of length L.  On entry a[q] = x_in[j + q*TPT]; on exit
 // a[q] = X[j + q*TPT] (unscaled).  x is this transform's LDS region
-// (lds_size(L) entries).  Every thread of the workgroup must call this the
-// same number of times (it contains workgroup barriers when L > 16).
-template <int L, bool INV>
-__device__ __forceinline__ void fft_reg(float2 (&a)[elems_per_thread(L)], int j, float2* x,
-                                        const float2* __restrict__ blob) {
+// (lds_region_bytes(L, .) bytes).  Every thread of the workgroup must call
+// this the same number of times (it contains workgroup barriers when L > 16).
+// tws: the global tables (kTwGlobal), the LDS copy (kTwLds) or this thread's
+// register array from load_twiddles_reg (kTwReg).
+template <int L, bool INV, int TWM = kTwGlobal>
+__device__ __forceinline__ void fft_reg(float2 (&a)[elems_per_thread(L)], int j, void* x,
+                                        const float2* __restrict__ tws) {
   if constexpr (num_stages(L) > 0) {
-    // Hide the table address from the optimiser: the twiddles of two
-    // transforms in one kernel are then loaded per transform, instead of
-    // being kept live in registers from the first one to the second.
-    const float2* tw = blob;
-    asm volatile("" : "+s"(tw));
+    // Hide the table address and the thread index from the optimiser: with
+    // two transforms in one kernel, twiddles and LDS addresses are then
+    // recomputed per transform instead of being held live from the first
+    // transform to the second.  (LDS and register tables are left alone:
+    // laundering an LDS pointer would turn its reads into flat loads.)
+    const float2* tw = tws;
+    if constexpr (TWM == kTwGlobal) asm volatile("" : "+s"(tw));
+    asm volatile("" : "+v"(j));
     stage_compute<L, 0, INV>(a, nullptr);
-    StageChain<L, 1, INV>::run(a, j, x, tw);
+    StageChain<L, 1, INV, TWM>::run(a, j, x, tw);
   }
 }
 

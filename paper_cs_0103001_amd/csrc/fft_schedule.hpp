@@ -48,16 +48,42 @@ FFTMI_HD constexpr int tw_stage_offset(int L, int s) {
 }
 FFTMI_HD constexpr int tw_blob_size(int L) { return tw_stage_offset(L, num_stages(L)); }
 
+// The same factors in the layout kept in LDS by the persistent kernels:
+// stage s >= 1 occupies (R-1)*NS entries, entry (r-1)*NS + k = e^{-2 pi i r k/(NS R)},
+// so that lanes with consecutive k read consecutive entries.
+FFTMI_HD constexpr int lds_tw_offset(int L, int s) {
+  int off = 0;
+  for (int i = 1; i < s; ++i) off += stage_ns(L, i) * (stage_radix(L, i) - 1);
+  return off;
+}
+FFTMI_HD constexpr int lds_tw_entries(int L) { return lds_tw_offset(L, num_stages(L)); }
+// LDS twiddles are used up to this length (2^12: 32640 bytes).
+constexpr int kLdsTwMaxLog2 = 12;
+FFTMI_HD constexpr int lds_tw_bytes(int L) {
+  return L <= (1 << kLdsTwMaxLog2) ? ((lds_tw_entries(L) * 8 + 255) / 256) * 256 : 0;
+}
+
 // LDS footprint of one transform: one padding slot per 16 entries so that the
 // stride-16 writes of a radix-16 pass fall into distinct banks.
 FFTMI_HD constexpr int lds_pad(int i) { return i + (i >> 4); }
 FFTMI_HD constexpr int lds_size(int L) { return L >= 16 ? L + L / 16 : L; }
 
-// LDS stride of one transform's region when `inter` transforms are interleaved
-// lane by lane inside a wavefront: offsetting consecutive regions by 32/inter
-// 8-byte slots puts their lanes in disjoint bank groups.
-FFTMI_HD constexpr int region_stride(int L, int inter) {
-  return lds_size(L) + (inter > 1 && inter <= 32 ? 32 / inter : 0);
+#ifndef FFTMI_SPLIT_X
+#define FFTMI_SPLIT_X 0
+#endif
+// Exchange real and imaginary parts through LDS one after the other.
+constexpr bool kSplitExchange = FFTMI_SPLIT_X != 0;
+constexpr int kLdsEntryBytes = kSplitExchange ? 4 : 8;
+
+// Bytes of one transform's LDS region when `inter` transforms are interleaved
+// lane by lane inside a wavefront: offsetting consecutive regions by a share
+// of the 64 four-byte banks puts their lanes in disjoint bank groups.
+#ifndef FFTMI_BANK_SPAN
+#define FFTMI_BANK_SPAN 128
+#endif
+FFTMI_HD constexpr int lds_region_bytes(int L, int inter) {
+  return kLdsEntryBytes *
+         (lds_size(L) + (inter > 1 && inter <= 32 ? (FFTMI_BANK_SPAN / kLdsEntryBytes) / inter : 0));
 }
 
 constexpr int kMaxLog2Row = 14;      // longest single-pass transform, 2^14

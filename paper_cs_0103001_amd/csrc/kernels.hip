@@ -1,11 +1,21 @@
 // kernels.hip -- gfx950 kernels of the FFT -> filter -> IFFT path and their
-// launchers.  Every kernel keeps a transform's data in registers (16 complex
-// values per thread), exchanges it through LDS between radix passes, and
-// touches HBM exactly once on the way in and once on the way out.
+// launchers.
+//
+// Every kernel is persistent and software-pipelined: a workgroup copies the
+// twiddle tables of its transform length into LDS once, loads its first tile,
+// then loops over tiles, issuing the global loads of the next tile before it
+// transforms the current one.  A transform keeps its data in registers (16
+// complex values per thread), exchanges it through LDS between radix passes
+// and touches HBM once on the way in and once on the way out.  With no global
+// loads inside the transform (the twiddles are in LDS), the next tile's loads
+// stay in flight for the whole computation.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <map>
 #include <mutex>
 #include <set>
+#include <tuple>
 #include <utility>
 
 #include "../../include/fftmi.h"
@@ -16,6 +26,62 @@ namespace fftmi {
 
 __device__ __forceinline__ int ilog2_pow2(int x) { return 31 - __clz(x); }
 
+// Dynamic LDS of the workgroup: [twiddle tables][per-transform regions].
+__device__ __forceinline__ char* lds_base() {
+  extern __shared__ float4 lds_raw[];
+  return reinterpret_cast<char*>(lds_raw);
+}
+
+#ifndef FFTMI_TWM
+#define FFTMI_TWM 2
+#endif
+
+template <int L>
+struct Shape {
+  static constexpr int E = elems_per_thread(L);
+  static constexpr int TPT = L / E;
+  // Workgroups hold at most 512 threads (one 2^14-point transform needs
+  // 1024): a thread may then use up to 256 VGPRs, enough for the current
+  // tile, the prefetched one and its twiddle factors.
+  static constexpr int LB = TPT > 512 ? 1024 : 512;
+  // Twiddles: in registers up to 2^12 points (30 complex values per thread),
+  // from the global tables beyond.
+  static constexpr int TWM = L <= (1 << kLdsTwMaxLog2) ? FFTMI_TWM : kTwGlobal;
+  static constexpr int TWB = TWM == kTwLds ? lds_tw_bytes(L) : 0;  // LDS bytes they take
+};
+
+// A kernel's twiddle factors for thread index j: a register array loaded
+// once (kTwReg), an LDS copy made by the whole workgroup (kTwLds), or the
+// global tables (kTwGlobal).  The host passes the matching table layout.
+template <int L, int M = Shape<L>::TWM>
+struct Twiddles {
+  const float2* p;
+  __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int) : p(src) {}
+  __device__ __forceinline__ const float2* ptr() const { return p; }
+};
+template <int L>
+struct Twiddles<L, kTwLds> {
+  const float2* p;
+  __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int) {
+    extern __shared__ float4 lds_raw[];
+    float2* t = reinterpret_cast<float2*>(lds_raw);
+    load_twiddles_lds<L>(t, src, threadIdx.x, blockDim.x);
+    p = t;
+  }
+  __device__ __forceinline__ const float2* ptr() const { return p; }
+};
+template <int L>
+struct Twiddles<L, kTwReg> {
+  float2 r[reg_tw_count<L>()];
+  __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int j) { load_twiddles_reg<L>(r, j, src); }
+  __device__ __forceinline__ const float2* ptr() const { return r; }
+};
+
+template <int L>
+__device__ __forceinline__ char* regions() {
+  return lds_base() + Shape<L>::TWB;
+}
+
 // Make a per-thread pointer opaque to the optimiser so that addresses derived
 // from it are recomputed where they are used rather than held in registers
 // across a whole transform.
@@ -24,12 +90,41 @@ __device__ __forceinline__ void launder(T*& p) {
   asm volatile("" : "+v"(p));
 }
 
-// Workgroup index remap: consecutive indices are dispatched round-robin over
-// the 8 XCDs, each with its own L2.  Giving every XCD a contiguous range of
-// tiles keeps neighbouring tiles (which share cache lines) on one L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t i, int64_t grid) {
-  if ((grid & 7) == 0 && grid >= 16) return (i & 7) * (grid >> 3) + (i >> 3);
-  return i;
+// Tile order: workgroup slots are dispatched round-robin over the 8 XCDs
+// (each with its own L2).  Mapping slot n to tile (n % 8) * (T / 8) + n / 8
+// gives every XCD a contiguous range of tiles, so neighbouring tiles that
+// share cache lines are processed on one L2 at the same time.
+__device__ __forceinline__ int64_t tile_of(int64_t n, int64_t ntiles) {
+  if ((ntiles & 7) == 0 && ntiles >= 16) return (n & 7) * (ntiles >> 3) + (n >> 3);
+  return n;
+}
+
+// Global addressing: every access is (uniform tile base) + (32-bit lane
+// offset), which the hardware takes as an SGPR base plus one VGPR, instead of
+// a 64-bit address per element.
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, unsigned off) {
+  return __ldg(base + off);
+}
+
+// A lane offset made opaque where it is used: the per-element offsets
+// lane + q*stride are then computed next to the access instead of being
+// hoisted out of the tile loop and held in registers for its whole length.
+__device__ __forceinline__ unsigned fresh(unsigned v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Wait for a tile's loads before the tile loop.  The loop issues the next
+// tile's loads ahead of the current transform; if the first tile's loads were
+// still in flight at the loop head, the compiler's wait counting (merged over
+// the loop entry and its back edge) would make every iteration wait for its
+// own prefetch before transforming.  Passing the registers through an empty
+// asm statement completes those loads once, before the loop.
+template <int E>
+__device__ __forceinline__ void settle(float2 (&a)[E]) {
+#pragma unroll
+  for (int q = 0; q < E; ++q) asm volatile("" : "+v"(a[q].x), "+v"(a[q].y));
 }
 
 // ----------------------------------------------------------------- masks
@@ -47,178 +142,360 @@ __device__ __forceinline__ float powi_pos(float x, int n) {
   return r;
 }
 
-// a[q] *= H(u, v) for the column v owned by this thread, rows u = j + q*TPT.
+// Mask evaluators, one per kind (a template parameter of the column kernel so
+// that each kernel carries only its own state).  For the column v owned by a
+// thread, H is applied to rows u = j + q*TPT, q = 0..E-1.  With E = 16 and
+// j < TPT, u < N/2 exactly when q < 8, so the fftfreq value of row u is
+// j/N + (q/16 - [q >= 8]), an exact float sum.
 template <int L>
-__device__ __forceinline__ void apply_mask(float2 (&a)[elems_per_thread(L)], int j, int v, int M,
-                                           const MaskArgs& mk) {
+__device__ __forceinline__ float row_freq(float fj, int q) {
   constexpr int E = elems_per_thread(L), TPT = L / E;
-  switch (mk.kind) {
-    case FFT_MASK_TENSOR_F32: {
-      const float* col = mk.data + v;
-#pragma unroll
-      for (int q = 0; q < E; ++q) a[q] = cscale(a[q], __ldg(col + (int64_t)(j + q * TPT) * M));
-      break;
-    }
-    case FFT_MASK_GAUSSIAN: {
-      const float fv = freq_of(v, M, mk.inv_m);
-      const float fv2 = fv * fv;
-#pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const float fu = freq_of(j + q * TPT, L, mk.inv_n);
-        a[q] = cscale(a[q], expf(fmaf(fu, fu, fv2) * mk.gauss_coef));
-      }
-      break;
-    }
-    case FFT_MASK_BUTTERWORTH: {
-      const float fv = freq_of(v, M, mk.inv_m);
-      const float fv2 = fv * fv;
-#pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const float fu = freq_of(j + q * TPT, L, mk.inv_n);
-        const float qq = fmaf(fu, fu, fv2) * mk.inv_fc2;
-        const float p = (mk.order == 4) ? (qq * qq) * (qq * qq) : powi_pos(qq, mk.order);
-        a[q] = cscale(a[q], __builtin_amdgcn_rcpf(1.0f + p));
-      }
-      break;
-    }
-    case FFT_MASK_DISC: {
-      const double dv = (double)v - mk.c2;
-#pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const double du = (double)(j + q * TPT) - mk.c1;
-        if (du * du + dv * dv <= mk.disc_b2) a[q] = make_float2(0.f, 0.f);
-      }
-      break;
-    }
-    default:
-      break;
+  if constexpr (E == 16) {
+    return fj + ((float)q * (1.0f / 16.0f) - (q >= 8 ? 1.0f : 0.0f));
+  } else {  // short columns: the general fftfreq rule
+    (void)TPT;
+    const int u = (int)(fj * (float)L + 0.5f) + q * TPT;
+    return (float)(u < ((L + 1) >> 1) ? u : u - L) * (1.0f / (float)L);
   }
 }
 
-// ============================================================== kernel A
-// Batched transforms along contiguous rows, row-major in and out.
-template <int L, bool INV>
-__global__ __launch_bounds__(1024) void k_rows_rm(const void* __restrict__ in, int in_f32, void* __restrict__ out,
-                                                  int out_f32, int64_t rows, int tpw, float scale,
-                                                  const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E;
-  extern __shared__ float2 smem[];
-  const int tid = threadIdx.x;
-  const int t = tid / TPT, j = tid - t * TPT;
-  const int64_t row = (int64_t)blockIdx.x * tpw + t;
-  const bool ok = row < rows;
-  float2 a[E];
-  if (in_f32) {
-    const float* src = static_cast<const float*>(in) + row * L + j;
-#pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = make_float2(ok ? __ldg(src + q * TPT) : 0.f, 0.f);
-  } else {
-    const float2* src = static_cast<const float2*>(in) + row * L + j;
-#pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + q * TPT) : make_float2(0.f, 0.f);
+template <int L, int MK>
+struct MaskEval;
+
+template <int L>
+struct MaskEval<L, FFT_MASK_NONE> {
+  __device__ __forceinline__ MaskEval(const MaskArgs&, int, int, int) {}
+  __device__ __forceinline__ void apply(float2 (&)[elems_per_thread(L)], int, const MaskArgs&) const {}
+};
+
+template <int L>
+struct MaskEval<L, FFT_MASK_BUTTERWORTH> {
+  float fj, fv2;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
+      : fj((float)j * (1.0f / (float)L)) {
+    const float fv = freq_of(v, M, mk.inv_m);
+    fv2 = fv * fv;
   }
-  fft_reg<L, INV>(a, j, smem + t * lds_size(L), tw);
-  if (!ok) return;
-  if (out_f32) {
-    float* dst = static_cast<float*>(out) + row * L + j;
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs& mk) const {
 #pragma unroll
-    for (int q = 0; q < E; ++q) dst[q * TPT] = a[q].x * scale;
-  } else {
-    float2* dst = static_cast<float2*>(out) + row * L + j;
+    for (int q = 0; q < elems_per_thread(L); ++q) {
+      const float fu = row_freq<L>(fj, q);
+      const float qq = fmaf(fu, fu, fv2) * mk.inv_fc2;
+      const float p = (mk.order == 4) ? (qq * qq) * (qq * qq) : powi_pos(qq, mk.order);
+      a[q] = cscale(a[q], __builtin_amdgcn_rcpf(1.0f + p));
+    }
+  }
+};
+
+template <int L>
+struct MaskEval<L, FFT_MASK_GAUSSIAN> {
+  float fj, fv2;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
+      : fj((float)j * (1.0f / (float)L)) {
+    const float fv = freq_of(v, M, mk.inv_m);
+    fv2 = fv * fv;
+  }
+  // exp(-r^2 / (2 sigma^2)) = 2^(r^2 * gauss_coef * log2(e))
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs& mk) const {
+    const float c = mk.gauss_coef * 1.44269504088896340736f;
 #pragma unroll
-    for (int q = 0; q < E; ++q) dst[q * TPT] = cscale(a[q], scale);
+    for (int q = 0; q < elems_per_thread(L); ++q) {
+      const float fu = row_freq<L>(fj, q);
+      a[q] = cscale(a[q], __builtin_amdgcn_exp2f(fmaf(fu, fu, fv2) * c));
+    }
+  }
+};
+
+template <int L>
+struct MaskEval<L, FFT_MASK_DISC> {
+  double dv2;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int, int v, int) {
+    const double dv = (double)v - mk.c2;
+    dv2 = dv * dv;
+  }
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int j, const MaskArgs& mk) const {
+    constexpr int TPT = L / elems_per_thread(L);
+#pragma unroll
+    for (int q = 0; q < elems_per_thread(L); ++q) {
+      const double du = (double)(j + q * TPT) - mk.c1;
+      if (fma(du, du, dv2) <= mk.disc_b2) a[q] = make_float2(0.f, 0.f);
+    }
+  }
+};
+
+// Tensor masks: H[u][v] = data[u*M + v], read for the thread's column after
+// the forward transform (base: column v of the tile, stride M per row).
+template <int L>
+struct MaskEval<L, FFT_MASK_TENSOR_F32> {
+  const float* col;
+  unsigned lane, qs;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
+      : col(mk.data + v), lane((unsigned)(j * M)), qs((unsigned)((L / elems_per_thread(L)) * M)) {}
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs&) const {
+    const unsigned l = fresh(lane);
+#pragma unroll
+    for (int q = 0; q < elems_per_thread(L); ++q) a[q] = cscale(a[q], __ldg(col + l + q * qs));
+  }
+};
+
+// ============================================================== kernel A
+// Batched transforms along contiguous rows, row-major in and out.  A tile is
+// tpw rows; the last tile may be partial.  The workgroup loops over tiles
+// (slot n, n + grid, ...) and prefetches the next tile into registers while
+// the current one is transformed.
+template <int L, bool INV>
+__global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict__ in, int in_f32, void* __restrict__ out,
+                                                  int out_f32, int64_t rows, int tpw, int ntiles, float scale,
+                                                  const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
+  const int tid = threadIdx.x, t = tid / TPT, j = tid - t * TPT;
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L>() + t * lds_region_bytes(L, 1);
+  const unsigned lane = (unsigned)(t * L + j);
+  float2 a[E], nx[E];
+  auto load = [&](float2(&d)[E], int tile) __attribute__((always_inline)) {
+    const bool ok = (int64_t)tile * tpw + t < rows;
+    if (in_f32) {
+      const float* b = static_cast<const float*>(in) + (int64_t)tile * tpw * L;
+      {
+        const unsigned f_lane = fresh(lane);
+#pragma unroll
+        for (int q = 0; q < E; ++q) d[q] = make_float2(ok ? ld(b, f_lane + q * TPT) : 0.f, 0.f);
+      }
+    } else {
+      const float2* b = static_cast<const float2*>(in) + (int64_t)tile * tpw * L;
+      {
+        const unsigned f_lane = fresh(lane);
+#pragma unroll
+        for (int q = 0; q < E; ++q) d[q] = ok ? ld(b, f_lane + q * TPT) : make_float2(0.f, 0.f);
+      }
+    }
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  settle(a);
+  for (; n < ntiles; n += gridDim.x) {
+    const int tile = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    fft_reg<L, INV, S::TWM>(a, j, x, tw);
+    if ((int64_t)tile * tpw + t < rows) {
+      if (out_f32) {
+        float* b = static_cast<float*>(out) + (int64_t)tile * tpw * L;
+        {
+          const unsigned f_lane = fresh(lane);
+#pragma unroll
+          for (int q = 0; q < E; ++q) b[f_lane + q * TPT] = a[q].x * scale;
+        }
+      } else {
+        float2* b = static_cast<float2*>(out) + (int64_t)tile * tpw * L;
+        {
+          const unsigned f_lane = fresh(lane);
+#pragma unroll
+          for (int q = 0; q < E; ++q) b[f_lane + q * TPT] = cscale(a[q], scale);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = nx[q];
   }
 }
 
 // ============================================================== kernel B
-// Row pass, real input, two rows packed into one complex transform
-// z = f[2p] + i f[2p+1]; the two spectra are split with the Hermitian symmetry
-// of a real sequence's DFT: A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i.
+// Row pass of real rows into the blocked layout, rows packed in pairs into
+// complex transforms z = f[2p] + i f[2p+1]; the two spectra are split with the
+// Hermitian symmetry of a real sequence's DFT:
+// A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i.
+// A tile is npt pairs (a power of two) of one block of rb rows.
 template <int L, bool INV>
-__global__ __launch_bounds__(1024) void k_rows_to_blk_pair(const float* __restrict__ in, float2* __restrict__ ws,
-                                                           int rb, float scale, const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E, STR = lds_size(L);
-  extern __shared__ float2 smem[];
-  const int np = rb >> 1;
+__global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* __restrict__ in,
+                                                                   float2* __restrict__ ws, int rb, int npt,
+                                                                   int ntiles, float scale,
+                                                                   const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT, RBY = lds_region_bytes(L, 1);
+  char* reg = regions<L>();
+  const int np = rb >> 1;                      // pairs per block
+  const int lsub = ilog2_pow2(np / npt);       // tiles per block = np / npt
   const int tid = threadIdx.x, p = tid / TPT, j = tid - p * TPT;
-  const int64_t g = blockIdx.x;
-  const float* r0 = in + (g * rb + 2 * p) * (int64_t)L + j;
-  const float* r1 = r0 + L;
-  float2 a[E];
-#pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = make_float2(__ldg(r0 + q * TPT), __ldg(r1 + q * TPT));
-  float2* x = smem + p * STR;
-  fft_reg<L, INV>(a, j, x, tw);
-  __syncthreads();
-  scatter_natural<L>(a, j, x);
-  __syncthreads();
-  const int nt = np * TPT;
-  float4* dst = reinterpret_cast<float4*>(ws + g * (int64_t)L * rb);
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  char* x = reg + p * RBY;
+  const unsigned lane_in = (unsigned)(2 * p * L + j);
+  // epilogue lanes: pair pp of the tile, columns v = v0 + i*TPT; each writes
+  // rows 2pp, 2pp+1 as one float4 at float4 index v*np + pair
+  const int lnpt = ilog2_pow2(npt);
+  const int pp = tid & (npt - 1), v0 = tid >> lnpt;
+  const unsigned lane_out = (unsigned)(v0 * np + pp);
+  const char* xs = reg + pp * RBY;
   const float h = 0.5f * scale;
-  for (int v = tid; v < L; v += nt) {
-    const int vm = (L - v) & (L - 1);
-    for (int pp = 0; pp < np; ++pp) {
-      const float2 z = smem[pp * STR + lds_pad(v)];
-      const float2 zm = smem[pp * STR + lds_pad(vm)];
-      dst[(v * rb + 2 * pp) >> 1] = make_float4(h * (z.x + zm.x), h * (z.y - zm.y), h * (z.y + zm.y), h * (zm.x - z.x));
+  float2 a[E], nx[E];
+  auto first_row = [&](int t) __attribute__((always_inline)) {
+    return (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * 2 * npt;
+  };
+  auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
+    const float* b = in + first_row(t) * L;
+    const unsigned l = fresh(lane_in);
+#pragma unroll
+    for (int q = 0; q < E; ++q) d[q] = make_float2(ld(b, l + q * TPT), ld(b, l + L + q * TPT));
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  settle(a);
+  for (; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    fft_reg<L, INV, S::TWM>(a, j, x, tw);
+    // float4 base of this tile: block start plus the tile's first pair
+    float4* dst = reinterpret_cast<float4*>(ws + (int64_t)(t >> lsub) * L * rb) + (t & ((1 << lsub) - 1)) * npt;
+    const unsigned lo = fresh(lane_out);
+    if constexpr (kSplitExchange) {
+      float ax[E], by[E];
+      lds_barrier();
+      scatter_natural<L, kRe>(a, j, x);
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int v = v0 + i * TPT, vm = (L - v) & (L - 1);
+        const float zr = reinterpret_cast<const float*>(xs)[lds_pad(v)];
+        const float zmr = reinterpret_cast<const float*>(xs)[lds_pad(vm)];
+        ax[i] = h * (zr + zmr);
+        by[i] = h * (zmr - zr);
+      }
+      lds_barrier();
+      scatter_natural<L, kIm>(a, j, x);
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int v = v0 + i * TPT, vm = (L - v) & (L - 1);
+        const float zi = reinterpret_cast<const float*>(xs)[lds_pad(v)];
+        const float zmi = reinterpret_cast<const float*>(xs)[lds_pad(vm)];
+        dst[lo + i * TPT * np] = make_float4(ax[i], h * (zi - zmi), h * (zi + zmi), by[i]);
+      }
+    } else {
+      lds_barrier();
+      scatter_natural<L, kBoth>(a, j, x);
+      lds_barrier();
+#pragma unroll
+      for (int i = 0; i < E; ++i) {
+        const int v = v0 + i * TPT, vm = (L - v) & (L - 1);
+        const float2 z = reinterpret_cast<const float2*>(xs)[lds_pad(v)];
+        const float2 zm = reinterpret_cast<const float2*>(xs)[lds_pad(vm)];
+        dst[lo + i * TPT * np] =
+            make_float4(h * (z.x + zm.x), h * (z.y - zm.y), h * (z.y + zm.y), h * (zm.x - z.x));
+      }
     }
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = nx[q];
   }
 }
 
 // Row pass into the blocked layout, one transform per row (complex input, or
-// real input when rows cannot be paired).  Lanes interleave the RB rows.
+// real input when rows cannot be paired).  A tile is nt rows of one block
+// (rows g*rb + sub*nt ...); lanes interleave those nt rows.
 template <int L, bool INV>
-__global__ __launch_bounds__(1024) void k_rows_to_blk(const void* __restrict__ in, int in_f32, float2* __restrict__ ws,
-                                                      int rb, float scale, const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E;
-  extern __shared__ float2 smem[];
-  const int lrb = ilog2_pow2(rb);
-  const int tid = threadIdx.x, s = tid & (rb - 1), j = tid >> lrb;
-  const int64_t g = blockIdx.x;
-  const int64_t row = g * rb + s;
-  float2 a[E];
-  if (in_f32) {
-    const float* src = static_cast<const float*>(in) + row * L + j;
-#pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = make_float2(__ldg(src + q * TPT), 0.f);
-  } else {
-    const float2* src = static_cast<const float2*>(in) + row * L + j;
-#pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = __ldg(src + q * TPT);
-  }
-  fft_reg<L, INV>(a, j, smem + s * region_stride(L, rb), tw);
-  float2* dst = ws + g * (int64_t)L * rb + j * rb + s;
+__global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk(const void* __restrict__ in, int in_f32, float2* __restrict__ ws,
+                                                      int rb, int nt, int ntiles, float scale,
+                                                      const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
+  const int lnt = ilog2_pow2(nt), lsub = ilog2_pow2(rb / nt);
+  const int tid = threadIdx.x, sl = tid & (nt - 1), j = tid >> lnt;
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L>() + sl * lds_region_bytes(L, nt);
+  const unsigned lane_in = (unsigned)(sl * L + j), lane_out = (unsigned)(j * rb + sl);
   const int qs = TPT * rb;
+  // first row of tile t; its block starts at element (t >> lsub) * rb * L
+  auto row0 = [&](int t) __attribute__((always_inline)) {
+    return (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * nt;
+  };
+  float2 a[E], nx[E];
+  auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
+    if (in_f32) {
+      const float* b = static_cast<const float*>(in) + row0(t) * L;
+      {
+        const unsigned f_lane_in = fresh(lane_in);
 #pragma unroll
-  for (int q = 0; q < E; ++q) dst[q * qs] = cscale(a[q], scale);
+        for (int q = 0; q < E; ++q) d[q] = make_float2(ld(b, f_lane_in + q * TPT), 0.f);
+      }
+    } else {
+      const float2* b = static_cast<const float2*>(in) + row0(t) * L;
+      {
+        const unsigned f_lane_in = fresh(lane_in);
+#pragma unroll
+        for (int q = 0; q < E; ++q) d[q] = ld(b, f_lane_in + q * TPT);
+      }
+    }
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  settle(a);
+  for (; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    fft_reg<L, INV, S::TWM>(a, j, x, tw);
+    float2* b = ws + (int64_t)(t >> lsub) * L * rb + (t & ((1 << lsub) - 1)) * nt;
+    {
+      const unsigned f_lane_out = fresh(lane_out);
+#pragma unroll
+      for (int q = 0; q < E; ++q) b[f_lane_out + q * qs] = cscale(a[q], scale);
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = nx[q];
+  }
 }
 
 // ============================================================== kernel D
-// Row pass out of the blocked layout into row-major output.
-template <int L, bool INV>
-__global__ __launch_bounds__(1024) void k_rows_from_blk(const float2* __restrict__ ws, void* __restrict__ out,
-                                                        int out_f32, int rb, float scale,
-                                                        const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E;
-  extern __shared__ float2 smem[];
-  const int lrb = ilog2_pow2(rb);
-  const int tid = threadIdx.x, s = tid & (rb - 1), j = tid >> lrb;
-  const int64_t g = blockIdx.x;
-  const float2* src = ws + g * (int64_t)L * rb + j * rb + s;
+// Row pass out of the blocked layout into row-major output; tiles as above.
+template <int L, bool INV, bool F32>
+__global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __restrict__ ws, void* __restrict__ out,
+                                                                int rb, int nt, int ntiles, float scale,
+                                                                const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
+  const int lnt = ilog2_pow2(nt), lsub = ilog2_pow2(rb / nt);
+  const int tid = threadIdx.x, sl = tid & (nt - 1), j = tid >> lnt;
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L>() + sl * lds_region_bytes(L, nt);
+  const unsigned lane_in = (unsigned)(j * rb + sl), lane_out = (unsigned)(sl * L + j);
   const int qs = TPT * rb;
-  float2 a[E];
+  float2 a[E], nx[E];
+  auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
+    const float2* b = ws + (int64_t)(t >> lsub) * L * rb + (t & ((1 << lsub) - 1)) * nt;
+    {
+      const unsigned f_lane_in = fresh(lane_in);
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = __ldg(src + q * qs);
-  fft_reg<L, INV>(a, j, smem + s * region_stride(L, rb), tw);
-  const int64_t row = g * rb + s;
-  if (out_f32) {
-    float* dst = static_cast<float*>(out) + row * L + j;
+      for (int q = 0; q < E; ++q) d[q] = ld(b, f_lane_in + q * qs);
+    }
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  settle(a);
+  for (; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    fft_reg<L, INV, S::TWM>(a, j, x, tw);
+    const int64_t r0 = (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * nt;
+    if constexpr (F32) {
+      float* b = static_cast<float*>(out) + r0 * L;
+      {
+        const unsigned f_lane_out = fresh(lane_out);
 #pragma unroll
-    for (int q = 0; q < E; ++q) dst[q * TPT] = a[q].x * scale;
-  } else {
-    float2* dst = static_cast<float2*>(out) + row * L + j;
+        for (int q = 0; q < E; ++q) b[f_lane_out + q * TPT] = a[q].x * scale;
+      }
+    } else {
+      float2* b = static_cast<float2*>(out) + r0 * L;
+      {
+        const unsigned f_lane_out = fresh(lane_out);
 #pragma unroll
-    for (int q = 0; q < E; ++q) dst[q * TPT] = cscale(a[q], scale);
+        for (int q = 0; q < E; ++q) b[f_lane_out + q * TPT] = cscale(a[q], scale);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = nx[q];
   }
 }
 
@@ -239,179 +516,362 @@ __device__ __forceinline__ ColLanes col_lanes(int tid, int rb, int w) {
   return r;
 }
 
-template <int L>
-__global__ __launch_bounds__(1024) void k_cols_filter(float2* __restrict__ ws, float2* __restrict__ save, int M,
-                                                      int rb, int w, int tiles_per_img, MaskArgs mk,
-                                                      const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E;
-  extern __shared__ float2 smem[];
-  const int64_t i = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t img = i / tiles_per_img;
-  const int tile = (int)(i - img * tiles_per_img);
+// Forward column transform, mask, inverse column transform, in place.  A tile
+// is w columns of one image (ltiles = log2(M / w) tiles per image); the tile
+// base is image * L * M + v0 * rb and the lane offset jh*M*rb + c*rb + s.
+// Tensor-mask values are read after the forward transform.
+template <int L, int MK>
+__global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict__ ws, float2* __restrict__ save, int M,
+                                                      int rb, int w, int ltiles, int ntiles, MaskArgs mk,
+                                                      const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
-  const int v = tile * w + ln.c;
-  const int64_t off = img * (int64_t)L * M + (int64_t)ln.jh * M * rb + (int64_t)v * rb + ln.s;
-  const int qs = TPT * M;
-  float2* base = ws + off;
-  float2 a[E];
+  const Twiddles<L> twd(tws, ln.j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
+  const unsigned qs = (unsigned)(TPT * M);
+  const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
+  const int tmask = (1 << ltiles) - 1;
+  float2 a[E], nx[E];
+  auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
+    const float2* b = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    const unsigned f_lane = fresh(lane);
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = base[q * qs];
-  float2* x = smem + ln.c * region_stride(L, w);
-  fft_reg<L, false>(a, ln.j, x, tw);
-  if (save) {
-    float2* sb = save + off;
+    for (int q = 0; q < E; ++q) d[q] = b[f_lane + q * qs];
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  settle(a);
+  for (; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    float2* base = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    const int v = (t & tmask) * w + ln.c;
+    fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
+    if (save) {
+      float2* sb = save + (base - ws);
+      {
+        const unsigned f_lane = fresh(lane);
 #pragma unroll
-    for (int q = 0; q < E; ++q) sb[q * qs] = a[q];
-  }
-  apply_mask<L>(a, ln.j, v, M, mk);
-  fft_reg<L, true>(a, ln.j, x, tw);
-  launder(base);  // recompute the store addresses instead of keeping 16 live
+        for (int q = 0; q < E; ++q) sb[f_lane + q * qs] = a[q];
+      }
+    }
+    const MaskEval<L, MK> me(mk, ln.j, v, M);
+    me.apply(a, ln.j, mk);
+    fft_reg<L, true, S::TWM>(a, ln.j, x, tw);
+    {
+      const unsigned f_lane = fresh(lane);
 #pragma unroll
-  for (int q = 0; q < E; ++q) base[q * qs] = a[q];
-}
-
-template <int L, bool INV>
-__global__ __launch_bounds__(1024) void k_cols_single(const float2* __restrict__ ws, void* __restrict__ out,
-                                                      int out_f32, int M, int rb, int w, int tiles_per_img,
-                                                      float scale, const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E;
-  extern __shared__ float2 smem[];
-  const int64_t i = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t img = i / tiles_per_img;
-  const int tile = (int)(i - img * tiles_per_img);
-  const ColLanes ln = col_lanes(threadIdx.x, rb, w);
-  const int v = tile * w + ln.c;
-  const int qs = TPT * M;
-  const float2* src = ws + img * (int64_t)L * M + (int64_t)ln.jh * M * rb + (int64_t)v * rb + ln.s;
-  float2 a[E];
+      for (int q = 0; q < E; ++q) base[f_lane + q * qs] = a[q];
+    }
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = __ldg(src + q * qs);
-  fft_reg<L, INV>(a, ln.j, smem + ln.c * region_stride(L, w), tw);
-  const int64_t o = img * (int64_t)L * M + (int64_t)ln.j * M + v;
-  if (out_f32) {
-    float* dst = static_cast<float*>(out) + o;
-#pragma unroll
-    for (int q = 0; q < E; ++q) dst[q * qs] = a[q].x * scale;
-  } else {
-    float2* dst = static_cast<float2*>(out) + o;
-#pragma unroll
-    for (int q = 0; q < E; ++q) dst[q * qs] = cscale(a[q], scale);
+    for (int q = 0; q < E; ++q) a[q] = nx[q];
   }
 }
 
-template <int L>
-__global__ __launch_bounds__(1024) void k_cols_grad(const float2* __restrict__ ws, const float2* __restrict__ save,
-                                                    float* __restrict__ grad, int64_t nimg, int M, int rb, int w,
-                                                    float scale, const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E;
-  extern __shared__ float2 smem[];
-  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+// One column transform of the blocked layout, row-major output.
+template <int L, bool INV, bool F32>
+__global__ __launch_bounds__(Shape<L>::LB) void k_cols_single(const float2* __restrict__ ws, void* __restrict__ out,
+                                                              int M, int rb, int w, int ltiles, int ntiles,
+                                                      float scale, const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
-  const int v = tile * w + ln.c;
-  const int qs = TPT * M;
-  const int64_t off = (int64_t)ln.jh * M * rb + (int64_t)v * rb + ln.s;
+  const Twiddles<L> twd(tws, ln.j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
+  const unsigned qs = (unsigned)(TPT * M);
+  const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
+  const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
+  const int tmask = (1 << ltiles) - 1;
+  float2 a[E], nx[E];
+  auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
+    const float2* b = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    {
+      const unsigned f_lane = fresh(lane);
+#pragma unroll
+      for (int q = 0; q < E; ++q) d[q] = ld(b, f_lane + q * qs);
+    }
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  settle(a);
+  for (; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    fft_reg<L, INV, S::TWM>(a, ln.j, x, tw);
+    const int64_t o = (int64_t)(t >> ltiles) * L * M + (t & tmask) * w;
+    if constexpr (F32) {
+      float* b = static_cast<float*>(out) + o;
+      {
+        const unsigned f_lane_out = fresh(lane_out);
+#pragma unroll
+        for (int q = 0; q < E; ++q) b[f_lane_out + q * qs] = a[q].x * scale;
+      }
+    } else {
+      float2* b = static_cast<float2*>(out) + o;
+      {
+        const unsigned f_lane_out = fresh(lane_out);
+#pragma unroll
+        for (int q = 0; q < E; ++q) b[f_lane_out + q * qs] = cscale(a[q], scale);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = nx[q];
+  }
+}
+
+// Mask gradient: for every column tile, loop over the batch in order, forward-
+// transform the blocked rows of grad_y, multiply by conj(saved spectrum) and
+// accumulate the real part; grad = scale * sum.  The next image's tile is
+// prefetched while the current one is transformed.
+template <int L>
+__global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __restrict__ ws, const float2* __restrict__ save,
+                                                    float* __restrict__ grad, int nimg, int M, int rb, int w,
+                                                    int ntiles, float scale, const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
+  const ColLanes ln = col_lanes(threadIdx.x, rb, w);
+  const Twiddles<L> twd(tws, ln.j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
+  const unsigned qs = (unsigned)(TPT * M);
+  const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
+  const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
   const int64_t plane = (int64_t)L * M;
-  float2* x = smem + ln.c * region_stride(L, w);
-  float acc[E];
+  for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    float acc[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) acc[q] = 0.f;
-  for (int64_t b = 0; b < nimg; ++b) {
-    const float2* src = ws + b * plane + off;
-    float2 a[E];
+    for (int q = 0; q < E; ++q) acc[q] = 0.f;
+    float2 a[E], nx[E];
+    {
+      const float2* b = ws + t * w * rb;
+      {
+        const unsigned f_lane = fresh(lane);
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = __ldg(src + q * qs);
-    fft_reg<L, false>(a, ln.j, x, tw);
-    const float2* xs = save + b * plane + off;
-    launder(xs);
+        for (int q = 0; q < E; ++q) a[q] = ld(b, f_lane + q * qs);
+      }
+    }
+    settle(a);
+    for (int bi = 0; bi < nimg; ++bi) {
+      if (bi + 1 < nimg) {
+        const float2* b = ws + (bi + 1) * plane + t * w * rb;
+        {
+          const unsigned f_lane = fresh(lane);
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const float2 X = __ldg(xs + q * qs);
-      acc[q] = fmaf(X.x, a[q].x, fmaf(X.y, a[q].y, acc[q]));
+          for (int q = 0; q < E; ++q) nx[q] = ld(b, f_lane + q * qs);
+        }
+      }
+      fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
+      const float2* xs = save + bi * plane + t * w * rb;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const float2 X = ld(xs, lane + q * qs);
+        acc[q] = fmaf(X.x, a[q].x, fmaf(X.y, a[q].y, acc[q]));
+      }
+#pragma unroll
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
+    float* dst = grad + t * w;
+    {
+      const unsigned f_lane_out = fresh(lane_out);
+#pragma unroll
+      for (int q = 0; q < E; ++q) dst[f_lane_out + q * qs] = acc[q] * scale;
     }
   }
-  float* dst = grad + (int64_t)ln.j * M + v;
-#pragma unroll
-  for (int q = 0; q < E; ++q) dst[q * qs] = acc[q] * scale;
 }
 
 // ============================================================== kernel E
-// Strided column pass over a row-major [L][C] matrix (four-step long 1D).
+// Strided column pass over a row-major [L][C] matrix per batch entry (the
+// four-step long 1D transform).  twiddle_transpose: pass one (multiply by
+// W_N^{k1 n2} from two-level tables and store transposed as [C][L]).
 template <int L, bool INV>
-__global__ __launch_bounds__(1024) void k_cols_strided(const float2* __restrict__ in, float2* __restrict__ out,
-                                                       int C, int w, int tiles, int twiddle_transpose, float scale,
-                                                       const float2* __restrict__ tlo,
+__global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __restrict__ in, float2* __restrict__ out,
+                                                       int C, int w, int ltiles, int ntiles, int twiddle_transpose,
+                                                       float scale, const float2* __restrict__ tlo,
                                                        const float2* __restrict__ thi, int h,
-                                                       const float2* __restrict__ tw) {
-  constexpr int E = elems_per_thread(L), TPT = L / E;
-  extern __shared__ float2 smem[];
-  const int64_t i = xcd_tile(blockIdx.x, gridDim.x);
-  const int64_t b = i / tiles;
-  const int tile = (int)(i - b * tiles);
-  const int c0 = tile * w;
+                                                       const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
   const int lw = ilog2_pow2(w);
   const int tid = threadIdx.x, c = tid & (w - 1), j = tid >> lw;
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  const int rbytes = lds_region_bytes(L, w);
+  char* reg = regions<L>();
+  char* x = reg + c * rbytes;
   const int64_t N = (int64_t)L * C;
-  const int qs = TPT * C;
-  const float2* src = in + b * N + (int64_t)j * C + c0 + c;
-  float2 a[E];
+  const unsigned qs = (unsigned)(TPT * C);
+  const unsigned lane = (unsigned)(j * C + c);
+  const int tmask = (1 << ltiles) - 1;
+  float2 a[E], nx[E];
+  auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
+    const float2* b = in + (int64_t)(t >> ltiles) * N + (t & tmask) * w;
+    {
+      const unsigned f_lane = fresh(lane);
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = __ldg(src + q * qs);
-  const int stride = region_stride(L, w);
-  float2* x = smem + c * stride;
-  fft_reg<L, INV>(a, j, x, tw);
-  if (twiddle_transpose) {
-    const int n2 = c0 + c;
-    const int lomask = (1 << h) - 1;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-      const int t = (j + q * TPT) * n2;  // < N <= 2^24, exact
-      const float2 lo = __ldg(tlo + (t & lomask)), hi = __ldg(thi + (t >> h));
-      const float2 wv = make_float2(lo.x * hi.x - lo.y * hi.y, lo.x * hi.y + lo.y * hi.x);
-      a[q] = cmul_tw<INV>(a[q], wv);
+      for (int q = 0; q < E; ++q) d[q] = ld(b, f_lane + q * qs);
     }
-    __syncthreads();
-    scatter_natural<L>(a, j, x);
-    __syncthreads();
-    const int nthr = w * TPT;
-    const int lL = ilog2_pow2(L);
-    float2* dst = out + b * N + (int64_t)c0 * L;
-    for (int idx = tid; idx < w * L; idx += nthr) {
-      const int cc = idx >> lL, k = idx & (L - 1);
-      dst[idx] = cscale(smem[cc * stride + lds_pad(k)], scale);
-    }
-  } else {
-    float2* dst = out + b * N + (int64_t)j * C + c0 + c;
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  settle(a);
+  for (; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    const int64_t bo = (int64_t)(t >> ltiles) * N;
+    const int c0 = (t & tmask) * w;
+    fft_reg<L, INV, S::TWM>(a, j, x, tw);
+    if (twiddle_transpose) {
+      const int n2 = c0 + c;
+      const int lomask = (1 << h) - 1;
 #pragma unroll
-    for (int q = 0; q < E; ++q) dst[q * qs] = cscale(a[q], scale);
+      for (int q = 0; q < E; ++q) {
+        const int tt = (j + q * TPT) * n2;  // < N <= 2^24, exact
+        const float2 lo = tlo[tt & lomask], hi = thi[tt >> h];
+        const float2 wv = make_float2(lo.x * hi.x - lo.y * hi.y, lo.x * hi.y + lo.y * hi.x);
+        a[q] = cmul_tw<INV>(a[q], wv);
+      }
+      // transposed store through LDS: out[n2][k1], contiguous along k1
+      const int nthr = w * TPT;
+      const int lL = ilog2_pow2(L);
+      float2 o[E];
+      if constexpr (kSplitExchange) {
+        lds_barrier();
+        scatter_natural<L, kRe>(a, j, x);
+        lds_barrier();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int idx = tid + e * nthr, cc = idx >> lL, k = idx & (L - 1);
+          o[e].x = reinterpret_cast<const float*>(reg + cc * rbytes)[lds_pad(k)];
+        }
+        lds_barrier();
+        scatter_natural<L, kIm>(a, j, x);
+        lds_barrier();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int idx = tid + e * nthr, cc = idx >> lL, k = idx & (L - 1);
+          o[e].y = reinterpret_cast<const float*>(reg + cc * rbytes)[lds_pad(k)];
+        }
+      } else {
+        lds_barrier();
+        scatter_natural<L, kBoth>(a, j, x);
+        lds_barrier();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int idx = tid + e * nthr, cc = idx >> lL, k = idx & (L - 1);
+          o[e] = reinterpret_cast<const float2*>(reg + cc * rbytes)[lds_pad(k)];
+        }
+      }
+      float2* b = out + bo + (int64_t)c0 * L;
+#pragma unroll
+      for (int e = 0; e < E; ++e) b[(unsigned)(tid + e * nthr)] = cscale(o[e], scale);
+    } else {
+      float2* b = out + bo + c0;
+      {
+        const unsigned f_lane = fresh(lane);
+#pragma unroll
+        for (int q = 0; q < E; ++q) b[f_lane + q * qs] = cscale(a[q], scale);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = nx[q];
   }
 }
 
 // ============================================================== launchers
 namespace {
 
-std::mutex g_attr_mu;
+std::mutex g_mu;
 std::set<std::pair<const void*, int>> g_attr_done;
+std::map<std::tuple<const void*, int, int, int>, int> g_occ;
+std::map<int, int> g_cus;
 
 // Allow up to the full 160 KiB of LDS for a kernel (once per device).
-hipError_t allow_lds(const void* fn, int bytes) {
+hipError_t allow_lds(const void* fn, int bytes, int dev) {
   if (bytes <= 65536) return hipSuccess;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  std::lock_guard<std::mutex> lk(g_attr_mu);
   if (g_attr_done.count({fn, dev})) return hipSuccess;
-  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
   if (e == hipSuccess) g_attr_done.insert({fn, dev});
   return e;
 }
 
+// Persistent grid: as many workgroups as fit on the device at once (a
+// multiple of 8 when possible, for the XCD tile order), never more than the
+// number of tiles.
+// Workgroups of a persistent launch.  With k = ceil(ntiles / resident) tiles
+// for the busiest workgroup, ceil(ntiles / k) workgroups finish in the same
+// number of rounds as a full grid but keep every round equally populated, so
+// a bandwidth-bound pass does not end with a round run by a fraction of the
+// chip.  The count is rounded up to a multiple of 8 where that still fits, so
+// that a workgroup keeps its XCD's slot of the tile order on every round.
+inline int64_t persistent_grid(int64_t ntiles, int64_t resident) {
+  if (ntiles <= resident) return ntiles;
+  const int64_t k = (ntiles + resident - 1) / resident;
+  int64_t g = (ntiles + k - 1) / k;
+  const int64_t g8 = (g + 7) & ~int64_t(7);
+  return g >= 16 && g8 <= resident ? g8 : g;
+}
+
+// Optional cap on resident workgroups per CU (FFTMI_WG_PER_CU), for tuning.
+inline int wg_cap() {
+  const char* e = std::getenv("FFTMI_WG_PER_CU");
+  return e ? std::atoi(e) : 0;
+}
+
 template <typename... Args>
-hipError_t go(void (*k)(Args...), dim3 grid, dim3 block, int lds, hipStream_t st, Args... args) {
-  if (grid.x == 0) return hipSuccess;
-  hipError_t e = allow_lds(reinterpret_cast<const void*>(k), lds);
+hipError_t go(void (*k)(Args...), int64_t ntiles, int block, int lds, hipStream_t st, Args... args) {
+  if (ntiles <= 0) return hipSuccess;
+  const void* fn = reinterpret_cast<const void*>(k);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, grid, block, lds, st, args...);
+  int per_cu = 0, cus = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    e = allow_lds(fn, lds, dev);
+    if (e != hipSuccess) return e;
+    auto key = std::make_tuple(fn, block, lds, dev);
+    auto it = g_occ.find(key);
+    if (it == g_occ.end()) {
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, (size_t)lds);
+      if (e != hipSuccess) return e;
+      g_occ[key] = per_cu;
+    } else {
+      per_cu = it->second;
+    }
+    auto ic = g_cus.find(dev);
+    if (ic == g_cus.end()) {
+      e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+      if (e != hipSuccess) return e;
+      g_cus[dev] = cus;
+    } else {
+      cus = ic->second;
+    }
+  }
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  const int cap = wg_cap();
+  if (cap > 0 && per_cu > cap) per_cu = cap;
+  const int64_t grid = persistent_grid(ntiles, (int64_t)per_cu * cus);
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(block), (size_t)lds, st, args...);
   return hipGetLastError();
+}
+
+template <int L>
+constexpr int tw_bytes() {
+  return Shape<L>::TWB;
+}
+
+template <int L>
+constexpr int max_block() {
+  return Shape<L>::LB;
+}
+
+template <int L>
+const float2* twiddle_src(const Launch& lc) {
+  return Shape<L>::TWM == kTwLds ? lc.tw_lds : lc.tw;
 }
 
 #define FFTMI_LOG2_CASES(F) \
@@ -423,34 +883,78 @@ struct RowsRm {
                         const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     int tpw = TPT >= 256 ? 1 : 256 / TPT;
+    static_assert(TPT <= max_block<L>(), "block");
     if (rows < tpw) tpw = (int)(rows > 0 ? rows : 1);
-    const int lds = tpw * lds_size(L) * (int)sizeof(float2);
-    const dim3 grid((unsigned)((rows + tpw - 1) / tpw)), block(tpw * TPT);
+    const int lds = tw_bytes<L>() + tpw * lds_region_bytes(L, 1);
+    const int ntiles = (int)((rows + tpw - 1) / tpw);
+    const float2* tw = twiddle_src<L>(lc);
     if (inv)
-      return go(k_rows_rm<L, true>, grid, block, lds, lc.stream, in, (int)in_f32, out, (int)out_f32, rows, tpw,
-                scale, lc.tw);
-    return go(k_rows_rm<L, false>, grid, block, lds, lc.stream, in, (int)in_f32, out, (int)out_f32, rows, tpw, scale,
-              lc.tw);
+      return go(k_rows_rm<L, true>, ntiles, tpw * TPT, lds, lc.stream, in, (int)in_f32, out, (int)out_f32, rows, tpw,
+                ntiles, scale, tw);
+    return go(k_rows_rm<L, false>, ntiles, tpw * TPT, lds, lc.stream, in, (int)in_f32, out, (int)out_f32, rows, tpw,
+              ntiles, scale, tw);
   }
 };
+
+// Real-row pairs per tile of the packed row pass: one whole block of rb rows
+// (rb / 2 pairs) while that fits the workgroup and LDS limits.
+template <int L>
+int pair_per_tile(int rb) {
+  constexpr int TPT = threads_per_transform(L);
+  int npt = rb / 2;
+  if (const char* e = std::getenv("FFTMI_PAIR_NPT")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= npt && (v & (v - 1)) == 0) npt = v;
+  }
+  while (npt > 1 && (npt * TPT > max_block<L>() || tw_bytes<L>() + npt * lds_region_bytes(L, 1) > kLdsBytes))
+    npt /= 2;
+  return npt;
+}
+
+// Rows per tile of the blocked row passes: the most that fit in LDS.
+template <int L>
+int rows_per_tile(int rb) {
+  // aim at 256-thread workgroups (several resident per CU)
+  int nt = rb;
+  while (nt > 1 && nt * threads_per_transform(L) > 256) nt /= 2;
+  if (const char* e = std::getenv("FFTMI_ROWS_NT")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= rb && (v & (v - 1)) == 0) nt = v;
+  }
+  while (nt > 1 && (tw_bytes<L>() + nt * lds_region_bytes(L, nt) > kLdsBytes ||
+                    nt * threads_per_transform(L) > max_block<L>()))
+    nt /= 2;
+  return nt;
+}
 
 template <int LG>
 struct RowsToBlk {
   static hipError_t run(bool inv, bool pair, const void* in, bool in_f32, float2* ws, int64_t blocks, int rb,
                         float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
-    const dim3 grid((unsigned)blocks);
-    if (pair) {
-      const int np = rb / 2;
-      const int lds = np * lds_size(L) * (int)sizeof(float2);
-      const float* fin = static_cast<const float*>(in);
-      if (inv) return go(k_rows_to_blk_pair<L, true>, grid, dim3(np * TPT), lds, lc.stream, fin, ws, rb, scale, lc.tw);
-      return go(k_rows_to_blk_pair<L, false>, grid, dim3(np * TPT), lds, lc.stream, fin, ws, rb, scale, lc.tw);
+    const float2* tw = twiddle_src<L>(lc);
+    if (pair && rb >= 2) {
+      // pairs per tile: aim at 256-thread workgroups, within LDS and block limits
+      int npt = pair_per_tile<L>(rb);
+      if (tw_bytes<L>() + npt * lds_region_bytes(L, 1) <= kLdsBytes && npt * TPT <= max_block<L>()) {
+        const int lds = tw_bytes<L>() + npt * lds_region_bytes(L, 1);
+        const float* fin = static_cast<const float*>(in);
+        const int64_t ntiles = blocks * (rb / 2 / npt);
+        if (inv)
+          return go(k_rows_to_blk_pair<L, true>, ntiles, npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles,
+                    scale, tw);
+        return go(k_rows_to_blk_pair<L, false>, ntiles, npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles,
+                  scale, tw);
+      }
     }
-    const int lds = rb * region_stride(L, rb) * (int)sizeof(float2);
+    const int nt = rows_per_tile<L>(rb);
+    const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
+    const int64_t ntiles = blocks * (rb / nt);
     if (inv)
-      return go(k_rows_to_blk<L, true>, grid, dim3(rb * TPT), lds, lc.stream, in, (int)in_f32, ws, rb, scale, lc.tw);
-    return go(k_rows_to_blk<L, false>, grid, dim3(rb * TPT), lds, lc.stream, in, (int)in_f32, ws, rb, scale, lc.tw);
+      return go(k_rows_to_blk<L, true>, ntiles, nt * TPT, lds, lc.stream, in, (int)in_f32, ws, rb, nt, (int)ntiles,
+                scale, tw);
+    return go(k_rows_to_blk<L, false>, ntiles, nt * TPT, lds, lc.stream, in, (int)in_f32, ws, rb, nt, (int)ntiles,
+              scale, tw);
   }
 };
 
@@ -459,10 +963,13 @@ struct RowsFromBlk {
   static hipError_t run(bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
                         const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
-    const int lds = rb * region_stride(L, rb) * (int)sizeof(float2);
-    const dim3 grid((unsigned)blocks), block(rb * TPT);
-    if (inv) return go(k_rows_from_blk<L, true>, grid, block, lds, lc.stream, ws, out, (int)out_f32, rb, scale, lc.tw);
-    return go(k_rows_from_blk<L, false>, grid, block, lds, lc.stream, ws, out, (int)out_f32, rb, scale, lc.tw);
+    const float2* tw = twiddle_src<L>(lc);
+    const int nt = rows_per_tile<L>(rb);
+    const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
+    const int64_t ntiles = blocks * (rb / nt);
+    auto k = inv ? (out_f32 ? k_rows_from_blk<L, true, true> : k_rows_from_blk<L, true, false>)
+                 : (out_f32 ? k_rows_from_blk<L, false, true> : k_rows_from_blk<L, false, false>);
+    return go(k, ntiles, nt * TPT, lds, lc.stream, ws, out, rb, nt, (int)ntiles, scale, tw);
   }
 };
 
@@ -472,9 +979,27 @@ struct ColsFilter {
                         const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = M / w;
-    const int lds = w * region_stride(L, w) * (int)sizeof(float2);
-    return go(k_cols_filter<L>, dim3((unsigned)(nimg * tiles)), dim3(w * TPT), lds, lc.stream, ws, save, M, rb, w,
-              tiles, mk, lc.tw);
+    const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
+    const int64_t ntiles = nimg * tiles;
+    const float2* tw = twiddle_src<L>(lc);
+    const int lt = ilog2c(tiles);
+    switch (mk.kind) {
+      case FFT_MASK_TENSOR_F32:
+        return go(k_cols_filter<L, FFT_MASK_TENSOR_F32>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+                  (int)ntiles, mk, tw);
+      case FFT_MASK_GAUSSIAN:
+        return go(k_cols_filter<L, FFT_MASK_GAUSSIAN>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+                  (int)ntiles, mk, tw);
+      case FFT_MASK_BUTTERWORTH:
+        return go(k_cols_filter<L, FFT_MASK_BUTTERWORTH>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+                  (int)ntiles, mk, tw);
+      case FFT_MASK_DISC:
+        return go(k_cols_filter<L, FFT_MASK_DISC>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+                  (int)ntiles, mk, tw);
+      default:
+        return go(k_cols_filter<L, FFT_MASK_NONE>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+                  (int)ntiles, mk, tw);
+    }
   }
 };
 
@@ -484,13 +1009,13 @@ struct ColsSingle {
                         float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = M / w;
-    const int lds = w * region_stride(L, w) * (int)sizeof(float2);
-    const dim3 grid((unsigned)(nimg * tiles)), block(w * TPT);
-    if (inv)
-      return go(k_cols_single<L, true>, grid, block, lds, lc.stream, ws, out, (int)out_f32, M, rb, w, tiles, scale,
-                lc.tw);
-    return go(k_cols_single<L, false>, grid, block, lds, lc.stream, ws, out, (int)out_f32, M, rb, w, tiles, scale,
-              lc.tw);
+    const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
+    const float2* tw = twiddle_src<L>(lc);
+    const int64_t ntiles = nimg * tiles;
+    const int lt = ilog2c(tiles);
+    auto k = inv ? (out_f32 ? k_cols_single<L, true, true> : k_cols_single<L, true, false>)
+                 : (out_f32 ? k_cols_single<L, false, true> : k_cols_single<L, false, false>);
+    return go(k, ntiles, w * TPT, lds, lc.stream, ws, out, M, rb, w, lt, (int)ntiles, scale, tw);
   }
 };
 
@@ -499,9 +1024,10 @@ struct ColsGrad {
   static hipError_t run(const float2* ws, const float2* save, float* grad, int64_t nimg, int M, int rb, int w,
                         float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
-    const int lds = w * region_stride(L, w) * (int)sizeof(float2);
-    return go(k_cols_grad<L>, dim3((unsigned)(M / w)), dim3(w * TPT), lds, lc.stream, ws, save, grad, nimg, M, rb, w,
-              scale, lc.tw);
+    const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
+    const int64_t ntiles = M / w;
+    return go(k_cols_grad<L>, ntiles, w * TPT, lds, lc.stream, ws, save, grad, (int)nimg, M, rb, w, (int)ntiles,
+              scale, twiddle_src<L>(lc));
   }
 };
 
@@ -511,23 +1037,25 @@ struct ColsStrided {
                         const float2* tlo, const float2* thi, int h, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = C / w;
-    const int lds = w * region_stride(L, w) * (int)sizeof(float2);
-    const dim3 grid((unsigned)(batch * tiles)), block(w * TPT);
+    const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
+    const float2* tw = twiddle_src<L>(lc);
+    const int64_t ntiles = batch * tiles;
+    const int lt = ilog2c(tiles);
     if (inv)
-      return go(k_cols_strided<L, true>, grid, block, lds, lc.stream, in, out, C, w, tiles, (int)twt, scale, tlo, thi,
-                h, lc.tw);
-    return go(k_cols_strided<L, false>, grid, block, lds, lc.stream, in, out, C, w, tiles, (int)twt, scale, tlo, thi, h,
-              lc.tw);
+      return go(k_cols_strided<L, true>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
+                scale, tlo, thi, h, tw);
+    return go(k_cols_strided<L, false>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
+              scale, tlo, thi, h, tw);
   }
 };
 
 }  // namespace
 
-#define FFTMI_DISPATCH(STRUCT, LOG2, ...)              \
-  switch (LOG2) {                                      \
-    FFTMI_LOG2_CASES(FFTMI_CASE_##STRUCT)              \
-    default:                                           \
-      return hipErrorInvalidValue;                     \
+#define FFTMI_DISPATCH(STRUCT, LOG2, ...) \
+  switch (LOG2) {                         \
+    FFTMI_LOG2_CASES(FFTMI_CASE_##STRUCT) \
+    default:                              \
+      return hipErrorInvalidValue;        \
   }
 
 #define FFTMI_CASE_RowsRm(K) \
@@ -588,8 +1116,12 @@ hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, cons
   FFTMI_DISPATCH(ColsStrided, log2L)
 }
 
-int lds_bytes_rows_rm(int log2L, int tpw) { return tpw * lds_size(1 << log2L) * (int)sizeof(float2); }
-int lds_bytes_cols(int log2L, int w) { return w * region_stride(1 << log2L, w) * (int)sizeof(float2); }
-int lds_bytes_rows_blk(int log2L, int nt) { return nt * region_stride(1 << log2L, nt) * (int)sizeof(float2); }
+static int tw_lds_bytes_rt(int L) { return L <= (1 << kLdsTwMaxLog2) ? lds_tw_bytes(L) : 0; }
+int lds_bytes_rows_rm(int log2L, int tpw) { return tw_lds_bytes_rt(1 << log2L) + tpw * lds_region_bytes(1 << log2L, 1); }
+int lds_bytes_cols(int log2L, int w) { return tw_lds_bytes_rt(1 << log2L) + w * lds_region_bytes(1 << log2L, w); }
+int max_block_threads(int log2L) { return threads_per_transform(1 << log2L) > 512 ? 1024 : 512; }
+int lds_bytes_rows_blk(int log2L, int nt) {
+  return tw_lds_bytes_rt(1 << log2L) + nt * lds_region_bytes(1 << log2L, nt);
+}
 
 }  // namespace fftmi

@@ -26,7 +26,8 @@ struct MaskArgs {
 
 struct Launch {
   hipStream_t stream;
-  const float2* tw;  // twiddle blob for the transform length of this launch
+  const float2* tw;      // twiddle tables of the launch's transform length, [stage][k][r]
+  const float2* tw_lds;  // the same in the layout copied to LDS, [stage][r-1][k]
 };
 
 // Batched transforms along contiguous rows of length L = 2^log2L, row-major in
@@ -72,5 +73,7 @@ hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, cons
 int lds_bytes_rows_rm(int log2L, int tpw);
 int lds_bytes_cols(int log2L, int w);
 int lds_bytes_rows_blk(int log2L, int nt);
+// Most threads a workgroup of transforms of length 2^log2L may have.
+int max_block_threads(int log2L);
 
 }  // namespace fftmi

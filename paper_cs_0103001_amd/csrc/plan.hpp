@@ -19,6 +19,7 @@ int hip_fail(hipError_t e);
 
 int device_tables(int dev, DevTables** out);
 const float2* blob_for(const DevTables* t, int log2L);
+const float2* lds_blob_for(const DevTables* t, int log2L);
 int fourstep_tables(DevTables* t, int log2N, const float2** lo, const float2** hi, int* h);
 
 }  // namespace fftmi

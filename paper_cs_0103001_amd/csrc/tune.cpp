@@ -2,8 +2,9 @@
 //
 // A column tile reads W*RB*8 contiguous bytes per row block; wider tiles give
 // longer runs but fewer workgroups per CU (LDS: W * N * 8.5 bytes).  The
-// default asks for 64-byte runs; an autotuned value recorded for the shape
-// takes precedence.
+// default gives 256-thread workgroups, several of which share a CU (their
+// neighbouring tiles' runs meet in the XCD's L2); an autotuned value
+// recorded for the shape takes precedence.
 #include <algorithm>
 #include <cstdlib>
 
@@ -16,13 +17,16 @@ namespace fftmi {
 int widest_cols_tile(int log2L, int cols, int wmax) {
   const int tpt = threads_per_transform(1 << log2L);
   int w = 1;
-  while (w * 2 <= wmax && w * 2 <= cols && (w * 2) * tpt <= 1024 && lds_bytes_cols(log2L, w * 2) <= kLdsBytes)
+  while (w * 2 <= wmax && w * 2 <= cols && (w * 2) * tpt <= max_block_threads(log2L) &&
+         lds_bytes_cols(log2L, w * 2) <= kLdsBytes)
     w *= 2;
   return w;
 }
 
 int tuned_cols_width(const fftmi_plan* p) {
-  int w = std::max(1, 8 / p->rb);
+  // one 256-thread transform per workgroup for long columns, more for short
+  const int tpt = threads_per_transform(1 << p->log_n);
+  int w = std::max(1, 256 / tpt);
   if (const char* env = std::getenv("FFTMI_COLS_W")) {
     const int v = std::atoi(env);
     if (v >= 1 && (v & (v - 1)) == 0) w = v;
