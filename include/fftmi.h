@@ -134,14 +134,38 @@ int fft2d_filter_save(fft_plan_t plan, const void* in, void* out, const fft_mask
                       void* workspace, void* stream);
 int fft_spectrum_size(fft_plan_t plan, size_t* bytes);
 
-/* Mask gradient of y = 2D-IDFT(m . X) for a rank-2 complex-input plan:
+/* Mask gradient of y = 2D-IDFT(m . X) for a rank-2 plan:
  *   grad_mask[u][v] = sum_b Re( conj(X_b[u,v]) * (2D-IDFT^H g_b)[u,v] )
- * where g_b = grad_y (complex64 [B][N][M], the gradient of a real loss with
- * respect to y, as conj-Wirtinger "dL/dRe + i dL/dIm") and 2D-IDFT^H is the
- * adjoint transform (scale 1/M under FFT_NORM_PAPER).  The batch sum runs in
- * order b = 0..B-1 in float32; the result overwrites grad_mask (float32 [N][M]). */
+ * where g_b = grad_y (complex64 [B][N][M] whatever the plan's input type: the
+ * gradient of a real loss with respect to y, as conj-Wirtinger
+ * "dL/dRe + i dL/dIm") and 2D-IDFT^H is the adjoint transform (eq. 5's sums
+ * with the 2D-IDFT's scale, 1/M under FFT_NORM_PAPER).  X is the spectrum
+ * saved by fft2d_filter_save with the same plan shape.  The batch sum is taken
+ * in float32 over runs of consecutive images, each run in order b0..b1-1, and
+ * the runs added in order (deterministic); the result overwrites grad_mask
+ * (float32 [N][M], device).  Errors: FFT_ERR_ARG (bad plan, null pointers),
+ * FFT_ERR_STATE (not a rank-2 plan, or another device current),
+ * FFT_ERR_WORKSPACE, FFT_ERR_HIP. */
 int fft2d_filter_mask_grad(fft_plan_t plan, const void* grad_y, const void* spectrum, float* grad_mask,
                            void* workspace, void* stream);
+
+/* Mask gradient of the filtered mean-squared error, in the form that stays
+ * accurate where y is close to the target.  For y_b = 2D-IDFT(m . X_b),
+ * X_b = 2D-DFT(x_b) and a loss L = (weight/2) sum_b sum |y_b - c_b|^2:
+ *   dL/dm = weight * sum_b [ Re(conj X_b . 2D-IDFT^H (x_b - c_b))
+ *                            + (a_inv / a_fwd) (m - 1) |X_b|^2 ]
+ * because 2D-DFT(y_b - c_b) = (m - 1) X_b + 2D-DFT(x_b - c_b) (the transform
+ * pair of eq. 5 and the 2D-IDFT inverts exactly), where a_fwd and a_inv are
+ * the forward and inverse scales (N/M for FFT_NORM_PAPER).  At m = 1 no
+ * difference y - c of nearly equal values is formed.
+ *   resid     x - c per image: float32 [B][N][M] for an FFT_IN_REAL_F32 plan,
+ *             complex64 otherwise (device)
+ *   spectrum  X saved by fft2d_filter_save with this plan (device)
+ *   mask      m, float32 [N][M] row-major (device, required)
+ *   weight    e.g. 2 / (B N M) for the mean over all pixels
+ * Batch order and errors as fft2d_filter_mask_grad. */
+int fft2d_filter_mse_grad(fft_plan_t plan, const void* resid, const void* spectrum, const float* mask, float weight,
+                          float* grad_mask, void* workspace, void* stream);
 
 /* Ragged batch: `count` square images of power-of-two sizes sizes[i] (host
  * array, 1 <= sizes[i] <= 2048), packed back to back in one buffer (image i

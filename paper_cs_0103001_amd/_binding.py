@@ -64,6 +64,7 @@ _SIGS = {
     "fft2d_filter_stage": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _MASKP, _P, _P]),
     "fft2d_filter_save": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P, _P]),
     "fft2d_filter_mask_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "fft2d_filter_mse_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _P, _P, _P]),
     "fft_plan_ragged": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int64, _I64P, ctypes.c_uint32]),
     "fft2d_filter_ragged": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
     "fft_plan_destroy": (ctypes.c_int, [_P]),
@@ -156,6 +157,11 @@ def fft2d_filter_save(plan, inp, out, mask, spectrum, workspace, stream):
 def fft2d_filter_mask_grad(plan, grad_y, spectrum, grad_mask, workspace, stream):
     check(lib().fft2d_filter_mask_grad(plan, grad_y, spectrum, grad_mask, workspace, stream),
           "fft2d_filter_mask_grad")
+
+
+def fft2d_filter_mse_grad(plan, resid, spectrum, mask, weight, grad_mask, workspace, stream):
+    check(lib().fft2d_filter_mse_grad(plan, resid, spectrum, mask, float(weight), grad_mask, workspace, stream),
+          "fft2d_filter_mse_grad")
 
 
 def fft2d_filter_ragged(plan, inp, out, mask, workspace, stream):

@@ -174,6 +174,23 @@ def mask_grad(grad_y, spectrum, norm="paper"):
     return out
 
 
+def mse_grad(resid, spectrum, mask, weight, norm="paper"):
+    """weight * sum_b [Re(conj X_b . 2D-IDFT^H resid_b) + (a_inv/a_fwd)(m - 1)|X_b|^2]:
+    the mask gradient of (weight/2) sum |2D-IDFT(m . X) - c|^2 with resid = x - c."""
+    r, fin = _prep(resid)
+    N, M = r.shape[-2], r.shape[-1]
+    batch = r.numel() // (N * M)
+    if mask.dtype != torch.float32 or tuple(mask.shape) != (N, M):
+        raise ValueError("mask must be float32 [%d, %d]" % (N, M))
+    m = mask.contiguous()
+    plan = get_plan(2, (N, M), batch, fin | _NORM[norm], r.device)
+    out = torch.empty((N, M), dtype=torch.float32, device=r.device)
+    ws = plan.workspace()
+    B.fft2d_filter_mse_grad(plan.h, _ptr(r), _ptr(spectrum), _ptr(m), weight, _ptr(out), _ptr(ws),
+                            _stream(r.device))
+    return out
+
+
 def filter_ragged(packed, sizes, mask, real_output=False):
     """Ragged batch: square images of sizes[i]^2 packed back to back in one
     1D tensor (float32 or complex64); returns the filtered images, packed."""

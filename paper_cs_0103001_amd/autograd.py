@@ -43,3 +43,52 @@ class FFTFilterFn(torch.autograd.Function):
 def fft_filter(x, mask):
     """Filter x (float32 or complex64 [..., N, M]) with a learnable float32 mask [N, M]."""
     return FFTFilterFn.apply(x, mask)
+
+
+class FFTFilterMSEFn(torch.autograd.Function):
+    """L = mean over all pixels of |2D-IDFT(m . 2D-DFT(x)) - c|^2 for real x, c.
+
+    Evaluated through the exact identity y - c = 2D-IDFT((m - 1) . X) + (x - c),
+    so that neither the loss nor its mask gradient subtracts nearly equal
+    float32 values where the filter is close to the identity (m near 1, the
+    learnable mask's starting point).  Backward:
+      dL/dm = (2/K) sum_b [Re(conj X_b . 2D-IDFT^H(x_b - c_b)) + (N/M)(m - 1)|X_b|^2]
+      dL/dx = (2/K) Re(filter_m(y - c)),   dL/dc = -(2/K)(y - c),
+    with K = B N M and filter_m self-adjoint for a real mask.
+    """
+
+    @staticmethod
+    def forward(ctx, x, clean, mask):
+        if x.dtype != torch.float32 or clean.dtype != torch.float32:
+            raise TypeError("fft_filter_mse takes float32 images")
+        m = mask.detach()
+        d = (x - clean).contiguous()
+        u, spec = api.fft2d_filter(x, (m - 1.0).contiguous(), spectrum=True)
+        ur = torch.view_as_real(u)
+        re = ur[..., 0] + d
+        im = ur[..., 1]
+        K = clean.numel()
+        loss = (re.square().sum() + im.square().sum()) / K
+        ctx.save_for_backward(spec, d, re, im, m)
+        ctx.K = K
+        return loss
+
+    @staticmethod
+    def backward(ctx, gL):
+        spec, d, re, im, m = ctx.saved_tensors
+        K = ctx.K
+        gx = gc = gm = None
+        if ctx.needs_input_grad[2]:
+            gm = api.mse_grad(d, spec, m, 2.0 / K) * gL
+        if ctx.needs_input_grad[0]:
+            r = torch.complex(re, im)
+            gx = api.fft2d_filter(r, m, real_output=True) * (2.0 / K * gL)
+        if ctx.needs_input_grad[1]:
+            gc = re * (-2.0 / K * gL)
+        return gx, gc, gm
+
+
+def fft_filter_mse(noisy, clean, mask):
+    """Mean squared error between the filtered noisy batch and clean (both float32
+    [..., N, M]) with a learnable float32 mask [N, M]; differentiable in all three."""
+    return FFTFilterMSEFn.apply(noisy, clean, mask)

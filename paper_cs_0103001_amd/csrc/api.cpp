@@ -2,6 +2,7 @@
 // generation, and the pass sequence of every entry point.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -295,8 +296,15 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
     while (rb > 1 && threads_per_transform((int)N) % rb) rb /= 2;
     p->rb = rb;
     p->w = tuned_cols_width(p.get());
+    p->chunk = filter_chunk(N, M, batch);
     p->ws_bytes = (size_t)batch * (size_t)N * (size_t)M * sizeof(float2);
     p->spec_bytes = p->ws_bytes;
+    // the mask gradient's per-group partial sums follow the blocked data
+    p->grad_groups = grad_groups(M / p->w, batch);
+    if (p->grad_groups > 1) {
+      p->ws_bytes = (p->ws_bytes + 255) & ~(size_t)255;
+      p->ws_bytes += (size_t)p->grad_groups * (size_t)N * (size_t)M * sizeof(float);
+    }
   }
   plan_register(p.get());
   *out = p.release();
@@ -386,22 +394,34 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   const bool in_f32 = p->flags & FFT_IN_REAL_F32, out_f32 = p->flags & FFT_OUT_REAL_F32;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   float2* ws = static_cast<float2*>(workspace);
-  const int64_t blocks = p->batch * p->n / p->rb;
   const bool pair = in_f32 && p->rb >= 2;
   Launch lr = launch_for(st, p->tables, p->log_m);
   Launch lcn = launch_for(st, p->tables, p->log_n);
-  hipError_t e = hipSuccess;
-  if (stages & 1) {
-    e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, fwd_scale_2d(p), lr);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (stages & 2) {
-    e = launch_cols_filter(p->log_n, ws, static_cast<float2*>(spectrum), p->batch, (int)p->m, p->rb, p->w, mk, lcn);
-    if (e != hipSuccess) return hip_fail(e);
-  }
-  if (stages & 4) {
-    e = launch_rows_from_blk(p->log_m, true, ws, out, out_f32, blocks, p->rb, inv_scale_2d(p), lr);
-    if (e != hipSuccess) return hip_fail(e);
+  // The whole filter runs chunk by chunk: the three passes over one chunk of
+  // images before the next, with the chunk's intermediate small enough to
+  // stay in the memory-side cache between the passes.  A single stage covers
+  // the whole batch.
+  const int64_t plane = p->n * p->m;
+  const int64_t chunk = stages == 7 ? p->chunk : p->batch;
+  for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
+    const int64_t nb = std::min(chunk, p->batch - b0);
+    const int64_t blocks = nb * p->n / p->rb;
+    const char* cin = static_cast<const char*>(in) + (in ? b0 * plane * (in_f32 ? 4 : 8) : 0);
+    char* cout = static_cast<char*>(out) + (out ? b0 * plane * (out_f32 ? 4 : 8) : 0);
+    float2* cspec = spectrum ? static_cast<float2*>(spectrum) + b0 * plane : nullptr;
+    hipError_t e = hipSuccess;
+    if (stages & 1) {
+      e = launch_rows_to_blk(p->log_m, false, pair, cin, in_f32, ws, blocks, p->rb, fwd_scale_2d(p), lr);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    if (stages & 2) {
+      e = launch_cols_filter(p->log_n, ws, cspec, nb, (int)p->m, p->rb, p->w, mk, lcn);
+      if (e != hipSuccess) return hip_fail(e);
+    }
+    if (stages & 4) {
+      e = launch_rows_from_blk(p->log_m, true, ws, cout, out_f32, blocks, p->rb, inv_scale_2d(p), lr);
+      if (e != hipSuccess) return hip_fail(e);
+    }
   }
   return FFT_OK;
 }
@@ -422,8 +442,12 @@ int fft2d_filter_save(fft_plan_t p, const void* in, void* out, const fft_mask* m
   return filter_impl(p, in, out, mask, spectrum, workspace, stream, 7);
 }
 
-int fft2d_filter_mask_grad(fft_plan_t p, const void* grad_y, const void* spectrum, float* grad_mask,
-                           void* workspace, void* stream) {
+// Mask gradient from a saved spectrum: in_b (the incoming gradient, or the
+// residual of the fused MSE form) is forward-transformed in the blocked
+// layout, then the column kernel accumulates Re(conj X_b . T(in_b)) over the
+// batch in groups of consecutive images.
+static int grad_impl(fftmi_plan* p, const void* in, const void* spectrum, const float* mask, float weight,
+                     float* grad_mask, void* workspace, void* stream) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
   if (!grad_mask) return FFT_ERR_ARG;
@@ -434,20 +458,46 @@ int fft2d_filter_mask_grad(fft_plan_t p, const void* grad_y, const void* spectru
     hipError_t e = hipMemsetAsync(grad_mask, 0, (size_t)(p->n * p->m) * sizeof(float), st);
     return e == hipSuccess ? FFT_OK : hip_fail(e);
   }
-  if (!grad_y || !spectrum) return FFT_ERR_ARG;
+  if (!in || !spectrum) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
   int rc = check_plan(p, nullptr);
   if (rc != FFT_OK) return rc;
-  // adjoint of the 2D-IDFT: forward factors, scale 1/M (paper) or 1/(NM)
   float2* ws = static_cast<float2*>(workspace);
+  const bool in_f32 = mask && (p->flags & FFT_IN_REAL_F32);
+  const bool pair = in_f32 && p->rb % 2 == 0;
   const int64_t blocks = p->batch * p->n / p->rb;
   Launch lr = launch_for(st, p->tables, p->log_m);
-  hipError_t e = launch_rows_to_blk(p->log_m, false, false, grad_y, false, ws, blocks, p->rb, 1.0f, lr);
+  // unscaled forward transform of the rows; the adjoint's scale goes into w_lin
+  hipError_t e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
+  const float b = inv_scale_2d(p), a = fwd_scale_2d(p);
+  const float w_lin = weight * b, w_sq = weight * (b / a);
+  const int groups = p->grad_groups;
+  float* part = grad_mask;
+  if (groups > 1) {
+    const size_t off = ((size_t)p->batch * (size_t)p->n * (size_t)p->m * sizeof(float2) + 255) & ~(size_t)255;
+    part = reinterpret_cast<float*>(static_cast<char*>(workspace) + off);
+  }
   Launch lcn = launch_for(st, p->tables, p->log_n);
-  e = launch_cols_grad(p->log_n, ws, static_cast<const float2*>(spectrum), grad_mask, p->batch, (int)p->m, p->rb,
-                       p->w, inv_scale_2d(p), lcn);
-  return e == hipSuccess ? FFT_OK : hip_fail(e);
+  e = launch_cols_grad(p->log_n, ws, static_cast<const float2*>(spectrum), mask, part, p->batch, groups, (int)p->m,
+                       p->rb, p->w, w_lin, w_sq, lcn);
+  if (e != hipSuccess) return hip_fail(e);
+  if (groups > 1) {
+    e = launch_sum_groups(part, grad_mask, p->n * p->m, groups, st);
+    if (e != hipSuccess) return hip_fail(e);
+  }
+  return FFT_OK;
+}
+
+int fft2d_filter_mask_grad(fft_plan_t p, const void* grad_y, const void* spectrum, float* grad_mask,
+                           void* workspace, void* stream) {
+  return grad_impl(p, grad_y, spectrum, nullptr, 1.0f, grad_mask, workspace, stream);
+}
+
+int fft2d_filter_mse_grad(fft_plan_t p, const void* resid, const void* spectrum, const float* mask, float weight,
+                          float* grad_mask, void* workspace, void* stream) {
+  if (!mask && plan_live(p) && p->batch > 0) return FFT_ERR_ARG;
+  return grad_impl(p, resid, spectrum, mask, weight, grad_mask, workspace, stream);
 }
 
 int fft_plan_destroy(fft_plan_t p) {

@@ -11,6 +11,7 @@
 // stay in flight for the whole computation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -622,14 +623,21 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_single(const float2* __re
   }
 }
 
-// Mask gradient: for every column tile, loop over the batch in order, forward-
-// transform the blocked rows of grad_y, multiply by conj(saved spectrum) and
-// accumulate the real part; grad = scale * sum.  The next image's tile is
-// prefetched while the current one is transformed.
-template <int L>
+// Mask gradient.  A tile is (image group g, column tile): loop over the
+// group's images in order, forward-transform the blocked rows of the incoming
+// gradient (or residual), multiply by conj(saved spectrum X) and accumulate
+// the real part, prefetching the next image's tile meanwhile.  The group's
+// partial sum goes to part[g][u][v]:
+//   w_lin * sum_b Re(conj X_b . T_b)  (+ w_sq * (m - 1) * sum_b |X_b|^2  when MT)
+// where T_b is the unscaled transform.  Partials of consecutive groups are
+// added in group order by k_sum_groups, so the result does not depend on the
+// launch shape's timing.
+template <int L, bool MT>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __restrict__ ws, const float2* __restrict__ save,
-                                                    float* __restrict__ grad, int nimg, int M, int rb, int w,
-                                                    int ntiles, float scale, const float2* __restrict__ tws) {
+                                                            const float* __restrict__ mask, float* __restrict__ part,
+                                                            int nimg, int per_group, int M, int rb, int w, int ltiles,
+                                                            int ntiles, float w_lin, float w_sq,
+                                                            const float2* __restrict__ tws) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
@@ -640,46 +648,70 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
   const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
   const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
   const int64_t plane = (int64_t)L * M;
+  const int tmask = (1 << ltiles) - 1;
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    float acc[E];
+    const int g = t >> ltiles, ct = t & tmask;
+    const int b0 = g * per_group, b1 = min(nimg, b0 + per_group);
+    float acc[E], acc2[E];
 #pragma unroll
-    for (int q = 0; q < E; ++q) acc[q] = 0.f;
+    for (int q = 0; q < E; ++q) acc[q] = acc2[q] = 0.f;
     float2 a[E], nx[E];
     {
-      const float2* b = ws + t * w * rb;
+      const float2* b = ws + b0 * plane + ct * w * rb;
+      const unsigned f_lane = fresh(lane);
+#pragma unroll
+      for (int q = 0; q < E; ++q) a[q] = ld(b, f_lane + q * qs);
+    }
+    settle(a);
+    for (int bi = b0; bi < b1; ++bi) {
+      if (bi + 1 < b1) {
+        const float2* b = ws + (bi + 1) * plane + ct * w * rb;
+        const unsigned f_lane = fresh(lane);
+#pragma unroll
+        for (int q = 0; q < E; ++q) nx[q] = ld(b, f_lane + q * qs);
+      }
+      fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
+      const float2* xs = save + bi * plane + ct * w * rb;
       {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) a[q] = ld(b, f_lane + q * qs);
-      }
-    }
-    settle(a);
-    for (int bi = 0; bi < nimg; ++bi) {
-      if (bi + 1 < nimg) {
-        const float2* b = ws + (bi + 1) * plane + t * w * rb;
-        {
-          const unsigned f_lane = fresh(lane);
-#pragma unroll
-          for (int q = 0; q < E; ++q) nx[q] = ld(b, f_lane + q * qs);
+        for (int q = 0; q < E; ++q) {
+          const float2 X = ld(xs, f_lane + q * qs);
+          acc[q] = fmaf(X.x, a[q].x, fmaf(X.y, a[q].y, acc[q]));
+          if constexpr (MT) acc2[q] = fmaf(X.x, X.x, fmaf(X.y, X.y, acc2[q]));
         }
-      }
-      fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
-      const float2* xs = save + bi * plane + t * w * rb;
-#pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const float2 X = ld(xs, lane + q * qs);
-        acc[q] = fmaf(X.x, a[q].x, fmaf(X.y, a[q].y, acc[q]));
       }
 #pragma unroll
       for (int q = 0; q < E; ++q) a[q] = nx[q];
     }
-    float* dst = grad + t * w;
-    {
-      const unsigned f_lane_out = fresh(lane_out);
+    const unsigned f_lane_out = fresh(lane_out);
+    float* dst = part + (int64_t)g * L * M + ct * w;
+    if constexpr (MT) {
+      const float* mrow = mask + ct * w;
 #pragma unroll
-      for (int q = 0; q < E; ++q) dst[f_lane_out + q * qs] = acc[q] * scale;
+      for (int q = 0; q < E; ++q)
+        dst[f_lane_out + q * qs] = fmaf(w_sq * (ld(mrow, f_lane_out + q * qs) - 1.0f), acc2[q], w_lin * acc[q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < E; ++q) dst[f_lane_out + q * qs] = w_lin * acc[q];
     }
+  }
+}
+
+// grad[i] = part[0][i] + part[1][i] + ... + part[G-1][i], in that order.
+__global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ part, float4* __restrict__ grad,
+                                                    int64_t n4, int groups) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    float4 s = part[i];
+    for (int g = 1; g < groups; ++g) {
+      const float4 v = part[g * n4 + i];
+      s.x += v.x;
+      s.y += v.y;
+      s.z += v.z;
+      s.w += v.w;
+    }
+    grad[i] = s;
   }
 }
 
@@ -1021,13 +1053,19 @@ struct ColsSingle {
 
 template <int LG>
 struct ColsGrad {
-  static hipError_t run(const float2* ws, const float2* save, float* grad, int64_t nimg, int M, int rb, int w,
-                        float scale, const Launch& lc) {
+  static hipError_t run(const float2* ws, const float2* save, const float* mask, float* part, int64_t nimg,
+                        int groups, int M, int rb, int w, float w_lin, float w_sq, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
-    const int64_t ntiles = M / w;
-    return go(k_cols_grad<L>, ntiles, w * TPT, lds, lc.stream, ws, save, grad, (int)nimg, M, rb, w, (int)ntiles,
-              scale, twiddle_src<L>(lc));
+    const int ctiles = M / w;
+    const int per_group = (int)((nimg + groups - 1) / groups);
+    const int64_t ntiles = (int64_t)groups * ctiles;
+    const int lt = ilog2c(ctiles);
+    if (mask)
+      return go(k_cols_grad<L, true>, ntiles, w * TPT, lds, lc.stream, ws, save, mask, part, (int)nimg, per_group,
+                M, rb, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
+    return go(k_cols_grad<L, false>, ntiles, w * TPT, lds, lc.stream, ws, save, mask, part, (int)nimg, per_group, M,
+              rb, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
   }
 };
 
@@ -1075,7 +1113,7 @@ struct ColsStrided {
     return ColsSingle<K>::run(inv, ws, out, out_f32, nimg, M, rb, w, scale, lc);
 #define FFTMI_CASE_ColsGrad(K) \
   case K:                      \
-    return ColsGrad<K>::run(ws, save, grad, nimg, M, rb, w, scale, lc);
+    return ColsGrad<K>::run(ws, save, mask, part, nimg, groups, M, rb, w, w_lin, w_sq, lc);
 #define FFTMI_CASE_ColsStrided(K) \
   case K:                         \
     return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_lo, tw_hi, h, lc);
@@ -1105,9 +1143,20 @@ hipError_t launch_cols_single(int log2L, bool inv, const float2* ws, void* out, 
   FFTMI_DISPATCH(ColsSingle, log2L)
 }
 
-hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, float* grad, int64_t nimg, int M,
-                            int rb, int w, float scale, const Launch& lc) {
+hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, const float* mask, float* part,
+                            int64_t nimg, int groups, int M, int rb, int w, float w_lin, float w_sq,
+                            const Launch& lc) {
   FFTMI_DISPATCH(ColsGrad, log2L)
+}
+
+hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int groups, hipStream_t stream) {
+  if (n % 4) return hipErrorInvalidValue;
+  const int64_t n4 = n / 4;
+  if (n4 == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n4 + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sum_groups, dim3((unsigned)blocks), dim3(256), 0, stream,
+                     reinterpret_cast<const float4*>(part), reinterpret_cast<float4*>(grad), n4, groups);
+  return hipGetLastError();
 }
 
 hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,

@@ -55,11 +55,17 @@ hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg,
 hipError_t launch_cols_single(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t nimg, int M,
                               int rb, int w, float scale, const Launch& lc);
 
-// Column pass for the mask gradient: for every column tile, loop over the
-// batch in order, forward-transform the blocked rows of grad_y, multiply by
-// conj(saved spectrum) and accumulate the real part; grad = scale * sum.
-hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, float* grad, int64_t nimg, int M,
-                            int rb, int w, float scale, const Launch& lc);
+// Column pass for the mask gradient over images split into `groups` runs of
+// consecutive images: for every (group, column tile), forward-transform the
+// blocked rows of each image in order, multiply by conj(saved spectrum X) and
+// accumulate the real part; part[g] = w_lin * sum + (mask ? w_sq * (m - 1) *
+// sum |X|^2 : 0).  With groups == 1, part may be the final gradient.
+hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, const float* mask, float* part,
+                            int64_t nimg, int groups, int M, int rb, int w, float w_lin, float w_sq,
+                            const Launch& lc);
+
+// grad = sum over g of part[g] (n floats each, n % 4 == 0), in group order.
+hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int groups, hipStream_t stream);
 
 // Strided column pass of the four-step long 1D transform over a row-major
 // [L][C] matrix per batch entry, tiles of w columns.  twiddle_transpose: pass

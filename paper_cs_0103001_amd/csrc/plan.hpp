@@ -34,12 +34,16 @@ struct fftmi_plan {
   fftmi::DevTables* tables = nullptr;
   // rank 2: rows per block of the blocked layout, column tile width
   int rb = 1, w = 1;
+  // rank 2: images per chunk of fft2d_filter (passes run chunk by chunk)
+  int64_t chunk = 1;
   // rank 1 beyond one LDS pass: four-step split N = N1 * N2
   bool fourstep = false;
   int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1, tw_h = 0;
   const float2* tw_lo = nullptr;
   const float2* tw_hi = nullptr;
   size_t ws_bytes = 0, spec_bytes = 0;
+  // rank 2: image groups of the mask-gradient column pass
+  int grad_groups = 1;
   fftmi::RaggedState* ragged = nullptr;
 };
 
@@ -55,6 +59,16 @@ int widest_cols_tile(int log2L, int cols, int wmax);
 
 // Column tile width for a rank-2 plan (autotuned value if one is cached).
 int tuned_cols_width(const fftmi_plan* p);
+
+// Images per chunk of the whole filter: the chunk's complex64 intermediate
+// stays within half of the memory-side cache (256 MiB on MI355X), so the
+// column pass and the inverse row pass read what the row pass just wrote from
+// the cache rather than from HBM.
+int64_t filter_chunk(int64_t N, int64_t M, int64_t batch);
+
+// Image groups of the mask-gradient column pass: enough (column tile, group)
+// work items to fill the chip, each group a run of consecutive images.
+int grad_groups(int64_t col_tiles, int64_t batch);
 
 void destroy_ragged_state(fftmi_plan* p);
 

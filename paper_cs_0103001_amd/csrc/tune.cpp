@@ -34,4 +34,21 @@ int tuned_cols_width(const fftmi_plan* p) {
   return widest_cols_tile(p->log_n, (int)p->m, w);
 }
 
+int64_t filter_chunk(int64_t N, int64_t M, int64_t batch) {
+  int64_t mib = 128;
+  if (const char* env = std::getenv("FFTMI_CHUNK_MB")) mib = std::atoll(env);
+  if (batch <= 1 || mib <= 0) return std::max<int64_t>(batch, 1);
+  const int64_t per_image = N * M * 8;
+  const int64_t c = (mib << 20) / std::max<int64_t>(per_image, 1);
+  return std::max<int64_t>(1, std::min(batch, c));
+}
+
+int grad_groups(int64_t col_tiles, int64_t batch) {
+  constexpr int64_t kTarget = 2048;  // work items: several per resident workgroup slot
+  if (batch <= 1 || col_tiles <= 0) return 1;
+  int64_t g = std::max<int64_t>(1, std::min<int64_t>(batch, kTarget / col_tiles));
+  const int64_t per = (batch + g - 1) / g;
+  return (int)((batch + per - 1) / per);
+}
+
 }  // namespace fftmi

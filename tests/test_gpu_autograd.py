@@ -1,6 +1,7 @@
 """Learnable-mask filter: GPU gradients against the FP64 oracle's analytic
 gradient, a GPU directional finite difference (eps = 1e-3, loss summed in
-FP64) and the adjoint dot-product identity."""
+FP64) and the adjoint dot-product identity; the fused filter+MSE form at the
+learnable workload's starting point (mask = 1)."""
 import numpy as np
 import pytest
 
@@ -127,3 +128,66 @@ def test_input_gradient_is_filter_of_upstream_gradient():
     g_ref = oracle.filter2(2.0 * (y_ref - clean) / clean.size, mask).real
     assert rel_l2(to_host(x.grad), g_ref, 2) < TOL
     del torch
+
+
+@pytest.mark.parametrize("B,N,M", [(2, 64, 64), (64, 64, 64), (3, 32, 128), (8, 1024, 1024)])
+def test_fused_mse_gradient_vs_oracle(B, N, M):
+    """Loss and mask gradient of fft_filter_mse against the oracle for random
+    masks (B = 64 at 64x64 spreads the batch over one image per group)."""
+    from paper_cs_0103001_amd.autograd import fft_filter_mse
+    noisy, clean = _pairs(B, N, M)
+    mask = np.random.default_rng(11 + B).uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    m = to_dev(mask).requires_grad_(True)
+    announce("fused mse grad B=%d %dx%d" % (B, N, M))
+    L = fft_filter_mse(to_dev(noisy), to_dev(clean), m)
+    L.backward()
+    _, L_ref, g_ref = oracle.loss_grad(noisy, clean, mask)
+    assert abs(float(L.detach()) - L_ref) / L_ref < 1e-5
+    err = rel_l2(to_host(m.grad), g_ref, 2)
+    print("grad relL2 = %.3e" % err)
+    assert err < TOL
+
+
+def test_fused_mse_gradient_at_mask_one():
+    """mask = 1 (the learnable workload's initial value), 1024x1024 images,
+    batch 4 of the batch-64 workload: the fused form meets the tolerance where
+    the generic route cannot."""
+    import torch
+    from paper_cs_0103001_amd.autograd import fft_filter_mse
+    noisy, clean = _pairs(4, 1024, 1024)
+    m = torch.ones((1024, 1024), dtype=torch.float32, device="cuda", requires_grad=True)
+    announce("fused mse grad at ones")
+    L = fft_filter_mse(to_dev(noisy), to_dev(clean), m)
+    L.backward()
+    _, L_ref, g_ref = oracle.loss_grad(noisy, clean, np.ones((1024, 1024)))
+    assert abs(float(L.detach()) - L_ref) / L_ref < 1e-6
+    err = rel_l2(to_host(m.grad), g_ref, 2)
+    print("grad relL2 at mask=1: %.3e" % err)
+    assert err < TOL
+
+
+def test_fused_mse_finite_difference_and_input_grads():
+    import torch
+    from paper_cs_0103001_amd.autograd import fft_filter_mse
+    B, N, M = 4, 256, 256
+    noisy, clean = _pairs(B, N, M)
+    xd, cd = to_dev(noisy), to_dev(clean)
+    rng = np.random.default_rng(17)
+    mask = rng.uniform(0.5, 1.0, (N, M)).astype(np.float32)
+    d = rng.choice([-1.0, 1.0], (N, M)).astype(np.float32)
+    m = to_dev(mask).requires_grad_(True)
+    x = xd.clone().requires_grad_(True)
+    c = cd.clone().requires_grad_(True)
+    fft_filter_mse(x, c, m).backward()
+    gd = float((m.grad.double() * to_dev(d).double()).sum())
+    eps = 1e-3
+    with torch.no_grad():
+        lp = float(fft_filter_mse(xd, cd, to_dev(mask + eps * d)).double())
+        lm = float(fft_filter_mse(xd, cd, to_dev(mask - eps * d)).double())
+    fd = (lp - lm) / (2 * eps)
+    print("FD %.6e  grad.d %.6e" % (fd, gd))
+    assert abs(fd - gd) <= 2e-2 * abs(gd)
+    y_ref, _, _ = oracle.loss_grad(noisy, clean, mask)
+    r = 2.0 * (y_ref - clean) / clean.size
+    assert rel_l2(to_host(x.grad), oracle.filter2(r, mask).real, 2) < TOL
+    assert rel_l2(to_host(c.grad), -r.real, 2) < TOL
