@@ -38,7 +38,7 @@ def log(msg):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "fft_core.hpp", "fft_schedule.hpp", "launch.hpp"):
+    for f in ("kernels.hip", "kernel_common.hpp", "fft_core.hpp", "fft_schedule.hpp", "launch.hpp"):
         with open(os.path.join(ROOT, "paper_cs_0103001_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

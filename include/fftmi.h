@@ -167,14 +167,41 @@ int fft2d_filter_mask_grad(fft_plan_t plan, const void* grad_y, const void* spec
 int fft2d_filter_mse_grad(fft_plan_t plan, const void* resid, const void* spectrum, const float* mask, float weight,
                           float* grad_mask, void* workspace, void* stream);
 
-/* Ragged batch: `count` square images of power-of-two sizes sizes[i] (host
- * array, 1 <= sizes[i] <= 2048), packed back to back in one buffer (image i
- * starts at element sum_{j<i} sizes[j]^2).  The filter runs as one persistent
- * launch with per-size schedules, captured in a HIP graph and replayed.
- * flags: FFT_IN_* and FFT_OUT_*. */
+/* Ragged batch: `count` square images of power-of-two sides sizes[i] (host
+ * array, copied; 1 <= sizes[i] <= 2048), packed back to back in one buffer:
+ * image i starts at element sum_{j<i} sizes[j]^2 and is row-major.  The plan
+ * builds the image table and the tile lists of the three passes on the
+ * current device (it owns that device memory and a capture stream until
+ * fft_plan_destroy).  flags: FFT_IN_*, FFT_OUT_*, FFT_NORM_*.  Errors:
+ * FFT_ERR_ARG, FFT_ERR_SIZE (a side that is not a power of two in range),
+ * FFT_ERR_NOMEM, FFT_ERR_HIP.  fft_workspace_size gives sum sizes[i]^2 * 8
+ * bytes.  If the environment variable FFTMI_TUNE_CACHE names a file holding a
+ * schedule recorded by fft_plan_tune for the same device, side list and
+ * flags, the plan starts from it. */
 int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32_t flags);
+
+/* fft2d_filter over every image of a ragged plan (Section 6 per image, eq. 5
+ * and the 2D-IDFT with each image's own N = M = side): one persistent launch
+ * per pass covering all sides, the launches of a call captured in a HIP graph
+ * that later calls with the same buffers and mask replay (a call with other
+ * buffers captures again).  Masks: FFT_MASK_NONE, GAUSSIAN, BUTTERWORTH (in
+ * cycles per pixel, so one mask serves every side); TENSOR and DISC return
+ * FFT_ERR_UNSUPPORTED.  Other errors as fft2d_filter. */
 int fft2d_filter_ragged(fft_plan_t plan, const void* in_packed, void* out_packed, const fft_mask* mask,
                         void* workspace, void* stream);
+
+/* Autotune a ragged plan's launch schedule on the caller's buffers (which it
+ * overwrites), blocking until done: every candidate (threads per workgroup
+ * 256 or 512, resident workgroups per CU as many as fit or 2, passes over the
+ * whole batch or over runs of images of at most 128 MiB of intermediate) is
+ * run once to warm up and timed over three calls with HIP events on `stream`;
+ * the fastest stays with the plan and, when FFTMI_TUNE_CACHE is set, is
+ * appended to that file.  FFT_ERR_UNSUPPORTED for other plan kinds. */
+int fft_plan_tune(fft_plan_t plan, const void* in_packed, void* out_packed, const fft_mask* mask, void* workspace,
+                  void* stream);
+
+/* The schedule a ragged plan uses (any pointer may be NULL). */
+int fft_plan_schedule(fft_plan_t plan, int* block, int* wg_cap, int64_t* chunk_bytes, int* order);
 
 /* Release a plan (and any graph it instantiated).  NULL is a no-op. */
 int fft_plan_destroy(fft_plan_t plan);

@@ -67,6 +67,9 @@ _SIGS = {
     "fft2d_filter_mse_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _P, _P, _P]),
     "fft_plan_ragged": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int64, _I64P, ctypes.c_uint32]),
     "fft2d_filter_ragged": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
+    "fft_plan_tune": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
+    "fft_plan_schedule": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                         _I64P, ctypes.POINTER(ctypes.c_int)]),
     "fft_plan_destroy": (ctypes.c_int, [_P]),
     "fft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fft_version": (ctypes.c_int, []),
@@ -167,6 +170,19 @@ def fft2d_filter_mse_grad(plan, resid, spectrum, mask, weight, grad_mask, worksp
 def fft2d_filter_ragged(plan, inp, out, mask, workspace, stream):
     check(lib().fft2d_filter_ragged(plan, inp, out, ctypes.byref(mask) if mask is not None else None, workspace,
                                     stream), "fft2d_filter_ragged")
+
+
+def fft_plan_tune(plan, inp, out, mask, workspace, stream):
+    check(lib().fft_plan_tune(plan, inp, out, ctypes.byref(mask) if mask is not None else None, workspace, stream),
+          "fft_plan_tune")
+
+
+def fft_plan_schedule(plan):
+    b, c, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ch = ctypes.c_int64()
+    check(lib().fft_plan_schedule(plan, ctypes.byref(b), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(o)),
+          "fft_plan_schedule")
+    return {"block": b.value, "wg_cap": c.value, "chunk_bytes": ch.value, "order": o.value}
 
 
 def fft_plan_destroy(plan):

@@ -208,3 +208,17 @@ def filter_ragged(packed, sizes, mask, real_output=False):
     ws = plan.workspace()
     B.fft2d_filter_ragged(plan.h, _ptr(x), _ptr(out), mk, _ptr(ws), _stream(x.device))
     return out
+
+
+def tune_ragged(packed, sizes, mask, real_output=False):
+    """Autotune the cached ragged plan for these sides on this batch (blocking);
+    returns the chosen schedule."""
+    x, fin = _prep(packed)
+    sizes = [int(s) for s in sizes]
+    flags = fin | (B.FFT_OUT_REAL_F32 if real_output else 0)
+    plan = get_plan(0, (), len(sizes), flags, x.device, ragged_sizes=sizes)
+    out = torch.empty(x.numel(), dtype=torch.float32 if real_output else torch.complex64, device=x.device)
+    mk, keep = _mask_struct(mask, 1, 1, x.device)
+    ws = plan.workspace()
+    B.fft_plan_tune(plan.h, _ptr(x), _ptr(out), mk, _ptr(ws), _stream(x.device))
+    return B.fft_plan_schedule(plan.h)

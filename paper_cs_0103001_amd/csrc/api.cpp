@@ -222,6 +222,11 @@ int fill_mask(const fft_mask* mk, const fftmi_plan* p, MaskArgs* out) {
 
 }  // namespace
 
+namespace fftmi {
+int plan_check(const fftmi_plan* p, int* dev_out) { return check_plan(const_cast<fftmi_plan*>(p), dev_out); }
+int mask_args(const fft_mask* mk, const fftmi_plan* p, MaskArgs* out) { return fill_mask(mk, p, out); }
+}  // namespace fftmi
+
 // =================================================================== C-ABI
 extern "C" {
 

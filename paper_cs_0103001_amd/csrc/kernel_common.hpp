@@ -1,0 +1,243 @@
+// kernel_common.hpp -- device helpers shared by the kernels of libfftmi: the
+// per-length launch shape, twiddle sources, LDS regions, tile order, global
+// addressing helpers and the mask evaluators.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "../../include/fftmi.h"
+#include "fft_core.hpp"
+#include "launch.hpp"
+
+namespace fftmi {
+
+__device__ __forceinline__ int ilog2_pow2(int x) { return 31 - __clz(x); }
+
+// Dynamic LDS of the workgroup: [twiddle tables][per-transform regions].
+__device__ __forceinline__ char* lds_base() {
+  extern __shared__ float4 lds_raw[];
+  return reinterpret_cast<char*>(lds_raw);
+}
+
+#ifndef FFTMI_TWM
+#define FFTMI_TWM 2
+#endif
+
+template <int L>
+struct Shape {
+  static constexpr int E = elems_per_thread(L);
+  static constexpr int TPT = L / E;
+  // Workgroups hold at most 512 threads (one 2^14-point transform needs
+  // 1024): a thread may then use up to 256 VGPRs, enough for the current
+  // tile, the prefetched one and its twiddle factors.
+  static constexpr int LB = TPT > 512 ? 1024 : 512;
+  // Twiddles: in registers up to 2^12 points (30 complex values per thread),
+  // from the global tables beyond.
+  static constexpr int TWM = L <= (1 << kLdsTwMaxLog2) ? FFTMI_TWM : kTwGlobal;
+  static constexpr int TWB = TWM == kTwLds ? lds_tw_bytes(L) : 0;  // LDS bytes they take
+};
+
+// A kernel's twiddle factors for thread index j: a register array loaded
+// once (kTwReg), an LDS copy made by the whole workgroup (kTwLds), or the
+// global tables (kTwGlobal).  The host passes the matching table layout.
+template <int L, int M = Shape<L>::TWM>
+struct Twiddles {
+  const float2* p;
+  __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int) : p(src) {}
+  __device__ __forceinline__ const float2* ptr() const { return p; }
+};
+template <int L>
+struct Twiddles<L, kTwLds> {
+  const float2* p;
+  __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int) {
+    extern __shared__ float4 lds_raw[];
+    float2* t = reinterpret_cast<float2*>(lds_raw);
+    load_twiddles_lds<L>(t, src, threadIdx.x, blockDim.x);
+    p = t;
+  }
+  __device__ __forceinline__ const float2* ptr() const { return p; }
+};
+template <int L>
+struct Twiddles<L, kTwReg> {
+  float2 r[reg_tw_count<L>()];
+  __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int j) { load_twiddles_reg<L>(r, j, src); }
+  __device__ __forceinline__ const float2* ptr() const { return r; }
+};
+
+template <int L>
+__device__ __forceinline__ char* regions() {
+  return lds_base() + Shape<L>::TWB;
+}
+
+// Make a per-thread pointer opaque to the optimiser so that addresses derived
+// from it are recomputed where they are used rather than held in registers
+// across a whole transform.
+template <typename T>
+__device__ __forceinline__ void launder(T*& p) {
+  asm volatile("" : "+v"(p));
+}
+
+// Tile order: workgroup slots are dispatched round-robin over the 8 XCDs
+// (each with its own L2).  Mapping slot n to tile (n % 8) * (T / 8) + n / 8
+// gives every XCD a contiguous range of tiles, so neighbouring tiles that
+// share cache lines are processed on one L2 at the same time.
+__device__ __forceinline__ int64_t tile_of(int64_t n, int64_t ntiles) {
+  if ((ntiles & 7) == 0 && ntiles >= 16) return (n & 7) * (ntiles >> 3) + (n >> 3);
+  return n;
+}
+
+// Global addressing: every access is (uniform tile base) + (32-bit lane
+// offset), which the hardware takes as an SGPR base plus one VGPR, instead of
+// a 64-bit address per element.
+template <typename T>
+__device__ __forceinline__ T ld(const T* __restrict__ base, unsigned off) {
+  return __ldg(base + off);
+}
+
+// A lane offset made opaque where it is used: the per-element offsets
+// lane + q*stride are then computed next to the access instead of being
+// hoisted out of the tile loop and held in registers for its whole length.
+__device__ __forceinline__ unsigned fresh(unsigned v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
+// Wait for a tile's loads before the tile loop.  The loop issues the next
+// tile's loads ahead of the current transform; if the first tile's loads were
+// still in flight at the loop head, the compiler's wait counting (merged over
+// the loop entry and its back edge) would make every iteration wait for its
+// own prefetch before transforming.  Passing the registers through an empty
+// asm statement completes those loads once, before the loop.
+template <int E>
+__device__ __forceinline__ void settle(float2 (&a)[E]) {
+#pragma unroll
+  for (int q = 0; q < E; ++q) asm volatile("" : "+v"(a[q].x), "+v"(a[q].y));
+}
+
+// ----------------------------------------------------------------- masks
+__device__ __forceinline__ float freq_of(int k, int n, float inv_n) {
+  return (float)(k < ((n + 1) >> 1) ? k : k - n) * inv_n;
+}
+
+__device__ __forceinline__ float powi_pos(float x, int n) {
+  float r = 1.0f;
+  while (n > 0) {
+    if (n & 1) r *= x;
+    x *= x;
+    n >>= 1;
+  }
+  return r;
+}
+
+// Mask evaluators, one per kind (a template parameter of the column kernel so
+// that each kernel carries only its own state).  For the column v owned by a
+// thread, H is applied to rows u = j + q*TPT, q = 0..E-1.  With E = 16 and
+// j < TPT, u < N/2 exactly when q < 8, so the fftfreq value of row u is
+// j/N + (q/16 - [q >= 8]), an exact float sum.
+template <int L>
+__device__ __forceinline__ float row_freq(float fj, int q) {
+  constexpr int E = elems_per_thread(L), TPT = L / E;
+  if constexpr (E == 16) {
+    return fj + ((float)q * (1.0f / 16.0f) - (q >= 8 ? 1.0f : 0.0f));
+  } else {  // short columns: the general fftfreq rule
+    (void)TPT;
+    const int u = (int)(fj * (float)L + 0.5f) + q * TPT;
+    return (float)(u < ((L + 1) >> 1) ? u : u - L) * (1.0f / (float)L);
+  }
+}
+
+template <int L, int MK>
+struct MaskEval;
+
+template <int L>
+struct MaskEval<L, FFT_MASK_NONE> {
+  __device__ __forceinline__ MaskEval(const MaskArgs&, int, int, int) {}
+  __device__ __forceinline__ void apply(float2 (&)[elems_per_thread(L)], int, const MaskArgs&) const {}
+};
+
+template <int L>
+struct MaskEval<L, FFT_MASK_BUTTERWORTH> {
+  float fj, fv2;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
+      : fj((float)j * (1.0f / (float)L)) {
+    const float fv = freq_of(v, M, mk.inv_m);
+    fv2 = fv * fv;
+  }
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs& mk) const {
+#pragma unroll
+    for (int q = 0; q < elems_per_thread(L); ++q) {
+      const float fu = row_freq<L>(fj, q);
+      const float qq = fmaf(fu, fu, fv2) * mk.inv_fc2;
+      const float p = (mk.order == 4) ? (qq * qq) * (qq * qq) : powi_pos(qq, mk.order);
+      a[q] = cscale(a[q], __builtin_amdgcn_rcpf(1.0f + p));
+    }
+  }
+};
+
+template <int L>
+struct MaskEval<L, FFT_MASK_GAUSSIAN> {
+  float fj, fv2;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
+      : fj((float)j * (1.0f / (float)L)) {
+    const float fv = freq_of(v, M, mk.inv_m);
+    fv2 = fv * fv;
+  }
+  // exp(-r^2 / (2 sigma^2)) = 2^(r^2 * gauss_coef * log2(e))
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs& mk) const {
+    const float c = mk.gauss_coef * 1.44269504088896340736f;
+#pragma unroll
+    for (int q = 0; q < elems_per_thread(L); ++q) {
+      const float fu = row_freq<L>(fj, q);
+      a[q] = cscale(a[q], __builtin_amdgcn_exp2f(fmaf(fu, fu, fv2) * c));
+    }
+  }
+};
+
+template <int L>
+struct MaskEval<L, FFT_MASK_DISC> {
+  double dv2;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int, int v, int) {
+    const double dv = (double)v - mk.c2;
+    dv2 = dv * dv;
+  }
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int j, const MaskArgs& mk) const {
+    constexpr int TPT = L / elems_per_thread(L);
+#pragma unroll
+    for (int q = 0; q < elems_per_thread(L); ++q) {
+      const double du = (double)(j + q * TPT) - mk.c1;
+      if (fma(du, du, dv2) <= mk.disc_b2) a[q] = make_float2(0.f, 0.f);
+    }
+  }
+};
+
+// Tensor masks: H[u][v] = data[u*M + v], read for the thread's column after
+// the forward transform (base: column v of the tile, stride M per row).
+template <int L>
+struct MaskEval<L, FFT_MASK_TENSOR_F32> {
+  const float* col;
+  unsigned lane, qs;
+  __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
+      : col(mk.data + v), lane((unsigned)(j * M)), qs((unsigned)((L / elems_per_thread(L)) * M)) {}
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs&) const {
+    const unsigned l = fresh(lane);
+#pragma unroll
+    for (int q = 0; q < elems_per_thread(L); ++q) a[q] = cscale(a[q], __ldg(col + l + q * qs));
+  }
+};
+
+// Column tiles of the blocked layout.  Lane order: row-in-block s fastest,
+// then column c of the tile, then the rest of the transform index j, so a
+// wavefront's load covers runs of W*RB*8 contiguous bytes.
+struct ColLanes {
+  int s, c, j, jh;
+};
+__device__ __forceinline__ ColLanes col_lanes(int tid, int rb, int w) {
+  const int lrb = ilog2_pow2(rb), lw = ilog2_pow2(w);
+  ColLanes r;
+  r.s = tid & (rb - 1);
+  r.c = (tid >> lrb) & (w - 1);
+  r.jh = tid >> (lrb + lw);
+  r.j = r.jh * rb + r.s;
+  return r;
+}
+
+}  // namespace fftmi

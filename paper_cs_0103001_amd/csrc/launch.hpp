@@ -75,6 +75,53 @@ hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, cons
                                int64_t batch, int C, int w, float scale, const float2* tw_lo, const float2* tw_hi,
                                int h, const Launch& lc);
 
+// Workgroups of a persistent launch.  With k = ceil(ntiles / resident) tiles
+// for the busiest workgroup, ceil(ntiles / k) workgroups finish in the same
+// number of rounds as a full grid but keep every round equally populated, so
+// a bandwidth-bound pass does not end with a round run by a fraction of the
+// chip.  The count is rounded up to a multiple of 8 where that still fits, so
+// that a workgroup keeps its XCD's slot of the tile order on every round.
+inline int64_t persistent_grid(int64_t ntiles, int64_t resident) {
+  if (ntiles <= resident) return ntiles;
+  const int64_t k = (ntiles + resident - 1) / resident;
+  int64_t g = (ntiles + k - 1) / k;
+  const int64_t g8 = (g + 7) & ~int64_t(7);
+  return g >= 16 && g8 <= resident ? g8 : g;
+}
+
+// ---------------------------------------------------------------- ragged
+constexpr int kRaggedMaxLog2 = 11;  // sides 1 .. 2048
+
+// One image of a ragged batch: element offset in the packed input/output and
+// in the workspace, log2 of its side and the rows per block of its blocked
+// workspace layout.
+struct RaggedImage {
+  int64_t off;
+  int64_t ws_off;
+  int lg;
+  int rb;
+};
+
+// FP32 twiddle tables (global layout) per log2 side.
+struct TwTable {
+  const float2* p[kRaggedMaxLog2 + 1];
+};
+
+// Dynamic LDS of a ragged pass with workgroups of `block` threads (any side).
+int ragged_lds_bytes(int block);
+
+// Persistent grid of one ragged pass over ntiles tiles (host queries only).
+// wg_cap > 0 limits resident workgroups per CU.
+hipError_t ragged_grid(int pass, bool in_f32, bool out_f32, int mask_kind, int block, int wg_cap, int ntiles,
+                       int* grid);
+
+// One pass (0: rows forward, 1: columns + mask, 2: rows inverse) over the
+// tiles {image, tile} of a ragged batch, one persistent launch of `grid`
+// workgroups.  Masks: NONE, GAUSSIAN, BUTTERWORTH.  Enqueues only.
+hipError_t launch_ragged_pass(int pass, const void* in, bool in_f32, float2* ws, void* out, bool out_f32,
+                              const RaggedImage* imgs, const int2* tiles, int ntiles, int block, int grid,
+                              const MaskArgs& mk, const TwTable& tw, bool numpy, hipStream_t st);
+
 // LDS bytes of one launch configuration (for the host's occupancy checks).
 int lds_bytes_rows_rm(int log2L, int tpw);
 int lds_bytes_cols(int log2L, int w);

@@ -7,6 +7,8 @@
 
 #include <string>
 
+#include "../../include/fftmi.h"
+
 namespace fftmi {
 
 struct DevTables;     // per-device twiddle tables (api.cpp)
@@ -71,5 +73,11 @@ int64_t filter_chunk(int64_t N, int64_t M, int64_t batch);
 int grad_groups(int64_t col_tiles, int64_t batch);
 
 void destroy_ragged_state(fftmi_plan* p);
+
+struct MaskArgs;
+// The plan is live and its device is current (FFT_OK, FFT_ERR_ARG, FFT_ERR_STATE, FFT_ERR_HIP).
+int plan_check(const fftmi_plan* p, int* dev_out);
+// Validate a C-ABI mask and turn it into kernel arguments for the plan's shape.
+int mask_args(const fft_mask* mk, const fftmi_plan* p, MaskArgs* out);
 
 }  // namespace fftmi

@@ -1,0 +1,314 @@
+// ragged_kernels.hip -- the three passes of the FFT -> filter -> IFFT path over
+// a ragged batch of square images with power-of-two sides 1 .. 2048.
+//
+// Each pass is one persistent kernel over a host-built list of tiles
+// {image, tile}.  A workgroup of T threads takes tiles from the list (slot n,
+// n + grid, ...) and switches on the tile's image size to the transform of
+// that length, so a single launch covers every size.  A tile is always
+// T/TPT(s) transforms of 16 points per thread (T*16 points), whatever the
+// image side s, which makes tiles of different images cost about the same.
+// Twiddles come from the global FP32 tables of each length (one per side).
+//
+// Image i of side s occupies elements [off, off + s*s) of the packed input
+// and output (row-major) and [ws_off, ws_off + s*s) of the workspace, where it
+// is kept in the blocked layout ((u / rb) * s + v) * rb + u % rb with
+// rb = min(4, TPT(s)), as in the uniform-batch passes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "../../include/fftmi.h"
+#include "fft_core.hpp"
+#include "kernel_common.hpp"
+#include "launch.hpp"
+
+namespace fftmi {
+
+namespace {
+
+constexpr int kRaggedMaxBlock = 512;
+
+// Forward row transforms of one tile: rows u = t*R + r of the image, f32 or
+// c64 input, scaled, stored into the blocked workspace.
+template <int L, bool IN_F32>
+__device__ __forceinline__ void rg_rows_fwd(const void* __restrict__ in, float2* __restrict__ ws,
+                                            const RaggedImage& im, int t, const float2* __restrict__ tw, char* lds,
+                                            float scale) {
+  constexpr int E = elems_per_thread(L), TPT = L / E;
+  const int R = (int)blockDim.x / TPT;
+  const int tid = threadIdx.x, r = tid / TPT, j = tid - r * TPT;
+  const int u = t * R + r;
+  const bool ok = u < L;
+  char* x = lds + r * lds_region_bytes(L, R);
+  float2 a[E];
+  if constexpr (IN_F32) {
+    const float* src = static_cast<const float*>(in) + im.off + (int64_t)(ok ? u : 0) * L;
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = make_float2(ok ? __ldg(src + j + q * TPT) : 0.f, 0.f);
+  } else {
+    const float2* src = static_cast<const float2*>(in) + im.off + (int64_t)(ok ? u : 0) * L;
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + j + q * TPT) : make_float2(0.f, 0.f);
+  }
+  fft_reg<L, false, kTwGlobal>(a, j, x, tw);
+  if (ok) {
+    const int rb = im.rb;
+    float2* dst = ws + im.ws_off + (int64_t)(u / rb) * L * rb + (u % rb);
+#pragma unroll
+    for (int q = 0; q < E; ++q) dst[(j + q * TPT) * rb] = cscale(a[q], scale);
+  }
+}
+
+// Column tile: w = T/TPT columns v = t*w + c, forward transform, mask,
+// inverse transform, in place in the blocked workspace.
+template <int L, int MK>
+__device__ __forceinline__ void rg_cols(float2* __restrict__ ws, const RaggedImage& im, int t, const MaskArgs& mk0,
+                                        const float2* __restrict__ tw, char* lds) {
+  constexpr int E = elems_per_thread(L), TPT = L / E;
+  const int w = (int)blockDim.x / TPT;
+  const int rb = im.rb;
+  const ColLanes ln = col_lanes(threadIdx.x, rb, w);
+  const int v = t * w + ln.c;
+  const bool ok = v < L;
+  char* x = lds + ln.c * lds_region_bytes(L, w);
+  float2* base = ws + im.ws_off + (int64_t)ln.jh * L * rb + (ok ? v : 0) * rb + ln.s;
+  const int64_t qs = (int64_t)TPT * L;
+  float2 a[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) a[q] = ok ? base[q * qs] : make_float2(0.f, 0.f);
+  fft_reg<L, false, kTwGlobal>(a, ln.j, x, tw);
+  MaskArgs mk = mk0;
+  mk.inv_n = mk.inv_m = 1.0f / (float)L;
+  const MaskEval<L, MK> me(mk, ln.j, v, L);
+  me.apply(a, ln.j, mk);
+  fft_reg<L, true, kTwGlobal>(a, ln.j, x, tw);
+  if (ok) {
+#pragma unroll
+    for (int q = 0; q < E; ++q) base[q * qs] = a[q];
+  }
+}
+
+// Inverse row transforms of one tile out of the blocked workspace.
+template <int L, bool OUT_F32>
+__device__ __forceinline__ void rg_rows_inv(const float2* __restrict__ ws, void* __restrict__ out,
+                                            const RaggedImage& im, int t, const float2* __restrict__ tw, char* lds,
+                                            float scale) {
+  constexpr int E = elems_per_thread(L), TPT = L / E;
+  const int R = (int)blockDim.x / TPT;
+  const int tid = threadIdx.x, r = tid / TPT, j = tid - r * TPT;
+  const int u = t * R + r;
+  const bool ok = u < L;
+  char* x = lds + r * lds_region_bytes(L, R);
+  const int rb = im.rb;
+  const float2* src = ws + im.ws_off + (int64_t)((ok ? u : 0) / rb) * L * rb + ((ok ? u : 0) % rb);
+  float2 a[E];
+#pragma unroll
+  for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + (j + q * TPT) * rb) : make_float2(0.f, 0.f);
+  fft_reg<L, true, kTwGlobal>(a, j, x, tw);
+  if (ok) {
+    if constexpr (OUT_F32) {
+      float* dst = static_cast<float*>(out) + im.off + (int64_t)u * L;
+#pragma unroll
+      for (int q = 0; q < E; ++q) dst[j + q * TPT] = a[q].x * scale;
+    } else {
+      float2* dst = static_cast<float2*>(out) + im.off + (int64_t)u * L;
+#pragma unroll
+      for (int q = 0; q < E; ++q) dst[j + q * TPT] = cscale(a[q], scale);
+    }
+  }
+}
+
+// Forward scale 1/s (eq. 5) or 1; inverse 1/s (2D-IDFT) or 1/s^2.
+__device__ __forceinline__ float rg_scale(int lg, int fwd, int numpy) {
+  const float s = (float)(1 << lg);
+  if (fwd) return numpy ? 1.0f : 1.0f / s;
+  return numpy ? 1.0f / (s * s) : 1.0f / s;
+}
+
+#define FFTMI_RG_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
+
+template <bool IN_F32>
+__global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_rows_fwd(const void* __restrict__ in, float2* __restrict__ ws,
+                                                                     const RaggedImage* __restrict__ imgs,
+                                                                     const int2* __restrict__ tiles, int ntiles,
+                                                                     TwTable tw, int numpy) {
+  char* lds = lds_base();
+  for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    const int2 tl = tiles[tile_of(n, ntiles)];
+    const RaggedImage im = imgs[tl.x];
+    const float sc = rg_scale(im.lg, 1, numpy);
+    switch (im.lg) {
+#define FFTMI_RG_ROWS_FWD(K)                                              \
+  case K:                                                                 \
+    rg_rows_fwd<1 << K, IN_F32>(in, ws, im, tl.y, tw.p[K], lds, sc);      \
+    break;
+      FFTMI_RG_CASES(FFTMI_RG_ROWS_FWD)
+#undef FFTMI_RG_ROWS_FWD
+      default:
+        break;
+    }
+  }
+}
+
+template <int MK>
+__global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_cols(float2* __restrict__ ws,
+                                                                 const RaggedImage* __restrict__ imgs,
+                                                                 const int2* __restrict__ tiles, int ntiles,
+                                                                 MaskArgs mk, TwTable tw) {
+  char* lds = lds_base();
+  for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    const int2 tl = tiles[tile_of(n, ntiles)];
+    const RaggedImage im = imgs[tl.x];
+    switch (im.lg) {
+#define FFTMI_RG_COLS(K)                                  \
+  case K:                                                 \
+    rg_cols<1 << K, MK>(ws, im, tl.y, mk, tw.p[K], lds);  \
+    break;
+      FFTMI_RG_CASES(FFTMI_RG_COLS)
+#undef FFTMI_RG_COLS
+      default:
+        break;
+    }
+  }
+}
+
+template <bool OUT_F32>
+__global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_rows_inv(const float2* __restrict__ ws, void* __restrict__ out,
+                                                                     const RaggedImage* __restrict__ imgs,
+                                                                     const int2* __restrict__ tiles, int ntiles,
+                                                                     TwTable tw, int numpy) {
+  char* lds = lds_base();
+  for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    const int2 tl = tiles[tile_of(n, ntiles)];
+    const RaggedImage im = imgs[tl.x];
+    const float sc = rg_scale(im.lg, 0, numpy);
+    switch (im.lg) {
+#define FFTMI_RG_ROWS_INV(K)                                              \
+  case K:                                                                 \
+    rg_rows_inv<1 << K, OUT_F32>(ws, out, im, tl.y, tw.p[K], lds, sc);    \
+    break;
+      FFTMI_RG_CASES(FFTMI_RG_ROWS_INV)
+#undef FFTMI_RG_ROWS_INV
+      default:
+        break;
+    }
+  }
+}
+
+// Persistent grid: resident workgroups (occupancy, optionally capped per
+// CU), at most one per tile, a multiple of 8 where possible.
+std::mutex g_rg_mu;
+std::map<std::tuple<const void*, int, int, int>, int> g_rg_occ;
+
+hipError_t rg_grid(const void* fn, int block, int lds, int cap, int ntiles, int* grid) {
+  int dev = 0, per_cu = 0, cus = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> lk(g_rg_mu);
+    auto key = std::make_tuple(fn, block, lds, dev);
+    auto it = g_rg_occ.find(key);
+    if (it == g_rg_occ.end()) {
+      if (lds > 64 * 1024) {
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+      }
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, (size_t)lds);
+      if (e != hipSuccess) return e;
+      g_rg_occ[key] = per_cu;
+    } else {
+      per_cu = it->second;
+    }
+  }
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  if (cap > 0 && per_cu > cap) per_cu = cap;
+  int64_t g = persistent_grid(ntiles, (int64_t)per_cu * cus);
+  *grid = (int)std::max<int64_t>(g, 1);
+  return hipSuccess;
+}
+
+}  // namespace
+
+int ragged_lds_bytes(int block) {
+  int most = 0;
+  for (int lg = 0; lg <= kRaggedMaxLog2; ++lg) {
+    const int L = 1 << lg, tpt = threads_per_transform(L);
+    const int per = block / tpt;  // transforms per tile
+    most = std::max(most, per * lds_region_bytes(L, per));
+  }
+  return most;
+}
+
+namespace {
+const void* ragged_kernel(int pass, bool in_f32, bool out_f32, int mask_kind) {
+  if (pass == 0)
+    return in_f32 ? reinterpret_cast<const void*>(k_ragged_rows_fwd<true>)
+                  : reinterpret_cast<const void*>(k_ragged_rows_fwd<false>);
+  if (pass == 2)
+    return out_f32 ? reinterpret_cast<const void*>(k_ragged_rows_inv<true>)
+                   : reinterpret_cast<const void*>(k_ragged_rows_inv<false>);
+  switch (mask_kind) {
+    case FFT_MASK_GAUSSIAN:
+      return reinterpret_cast<const void*>(k_ragged_cols<FFT_MASK_GAUSSIAN>);
+    case FFT_MASK_BUTTERWORTH:
+      return reinterpret_cast<const void*>(k_ragged_cols<FFT_MASK_BUTTERWORTH>);
+    case FFT_MASK_NONE:
+      return reinterpret_cast<const void*>(k_ragged_cols<FFT_MASK_NONE>);
+    default:
+      return nullptr;
+  }
+}
+}  // namespace
+
+hipError_t ragged_grid(int pass, bool in_f32, bool out_f32, int mask_kind, int block, int wg_cap, int ntiles,
+                       int* grid) {
+  *grid = 0;
+  if (ntiles <= 0) return hipSuccess;
+  if (block < 128 || block > kRaggedMaxBlock || (block & (block - 1))) return hipErrorInvalidValue;
+  const void* fn = ragged_kernel(pass, in_f32, out_f32, mask_kind);
+  if (!fn) return hipErrorInvalidValue;
+  return rg_grid(fn, block, ragged_lds_bytes(block), wg_cap, ntiles, grid);
+}
+
+hipError_t launch_ragged_pass(int pass, const void* in, bool in_f32, float2* ws, void* out, bool out_f32,
+                              const RaggedImage* imgs, const int2* tiles, int ntiles, int block, int grid,
+                              const MaskArgs& mk, const TwTable& tw, bool numpy, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  if (grid <= 0 || block < 128 || block > kRaggedMaxBlock || (block & (block - 1))) return hipErrorInvalidValue;
+  if (!ragged_kernel(pass, in_f32, out_f32, mk.kind)) return hipErrorInvalidValue;
+  const int lds = ragged_lds_bytes(block);
+  const int np = numpy ? 1 : 0;
+  if (pass == 0) {
+    if (in_f32)
+      hipLaunchKernelGGL(k_ragged_rows_fwd<true>, dim3(grid), dim3(block), (size_t)lds, st, in, ws, imgs, tiles,
+                         ntiles, tw, np);
+    else
+      hipLaunchKernelGGL(k_ragged_rows_fwd<false>, dim3(grid), dim3(block), (size_t)lds, st, in, ws, imgs, tiles,
+                         ntiles, tw, np);
+  } else if (pass == 1) {
+    if (mk.kind == FFT_MASK_GAUSSIAN)
+      hipLaunchKernelGGL(k_ragged_cols<FFT_MASK_GAUSSIAN>, dim3(grid), dim3(block), (size_t)lds, st, ws, imgs, tiles,
+                         ntiles, mk, tw);
+    else if (mk.kind == FFT_MASK_BUTTERWORTH)
+      hipLaunchKernelGGL(k_ragged_cols<FFT_MASK_BUTTERWORTH>, dim3(grid), dim3(block), (size_t)lds, st, ws, imgs,
+                         tiles, ntiles, mk, tw);
+    else
+      hipLaunchKernelGGL(k_ragged_cols<FFT_MASK_NONE>, dim3(grid), dim3(block), (size_t)lds, st, ws, imgs, tiles,
+                         ntiles, mk, tw);
+  } else {
+    if (out_f32)
+      hipLaunchKernelGGL(k_ragged_rows_inv<true>, dim3(grid), dim3(block), (size_t)lds, st, ws, out, imgs, tiles,
+                         ntiles, tw, np);
+    else
+      hipLaunchKernelGGL(k_ragged_rows_inv<false>, dim3(grid), dim3(block), (size_t)lds, st, ws, out, imgs, tiles,
+                         ntiles, tw, np);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fftmi

@@ -118,6 +118,31 @@ def ragged_image(i: int, size: int) -> np.ndarray:
     return star_field(size, size, n_stars, c["psf_sigma"], (c["seed"], i))
 
 
+def _ragged_one(args):
+    i, size = args
+    return ragged_image(i, size)
+
+
+def ragged_batch(sizes, workers: int = 1) -> np.ndarray:
+    """Images 0..len(sizes)-1 of the ragged batch packed back to back (float32,
+    image i row-major at offset sum_{j<i} sizes[j]^2).  workers > 1 generates
+    them in a spawned process pool (same values)."""
+    total = sum(int(s) * int(s) for s in sizes)
+    out = np.empty(total, dtype=np.float32)
+    jobs = list(enumerate(int(s) for s in sizes))
+    if workers > 1 and len(jobs) > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(workers) as pool:
+            imgs = pool.map(_ragged_one, jobs, chunksize=4)
+    else:
+        imgs = [_ragged_one(j) for j in jobs]
+    off = 0
+    for (i, s), im in zip(jobs, imgs):
+        out[off:off + s * s] = im.reshape(-1)
+        off += s * s
+    return out
+
+
 def learn_pair(b: int, N: int = None, M: int = None):
     """(noisy, clean) float32 images b of the learnable-mask batch.
 

@@ -1,0 +1,164 @@
+"""Ragged batches (mixed power-of-two sides in one persistent launch per
+pass, captured in a HIP graph, autotuned schedule) against the FP64 oracle,
+image by image."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import TOL, announce, need_gpu, rel_l2, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SIGMA_F = 0.1
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _split(flat, sizes):
+    out, off = [], 0
+    for s in sizes:
+        out.append(flat[off:off + s * s].reshape(s, s))
+        off += s * s
+    return out
+
+
+def _check(got_flat, imgs, sizes, mask_kind="gaussian"):
+    worst = 0.0
+    for g, im, s in zip(_split(got_flat, sizes), imgs, sizes):
+        if mask_kind == "gaussian":
+            m = oracle.mask_gaussian(s, s, SIGMA_F)
+        elif mask_kind == "butterworth":
+            m = oracle.mask_butterworth(s, s, 0.15, 4)
+        else:
+            m = np.ones((s, s))
+        ref = oracle.filter2(im, m, threads=4)
+        err = rel_l2(g, ref, 2)
+        worst = max(worst, err)
+        assert err < TOL, (s, err)
+    return worst
+
+
+def _images(sizes, seed0=100, complex_input=False):
+    imgs = [synth.ragged_image(seed0 + i, s) for i, s in enumerate(sizes)]
+    if complex_input:
+        rng = np.random.default_rng(seed0)
+        imgs = [(im + 1j * rng.standard_normal(im.shape).astype(np.float32)).astype(np.complex64) for im in imgs]
+    return imgs, np.concatenate([im.reshape(-1) for im in imgs])
+
+
+MIXED = [1, 2, 4, 8, 16, 32, 64, 128, 256, 512, 1024, 2048, 64, 8, 256, 1]
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "butterworth", "none"])
+def test_ragged_mixed_sides_vs_oracle(kind):
+    from paper_cs_0103001_amd import api
+    imgs, flat = _images(MIXED)
+    mask = {"gaussian": dict(kind="gaussian", sigma_f=SIGMA_F),
+            "butterworth": dict(kind="butterworth", cutoff=0.15, order=4), "none": None}[kind]
+    announce("ragged mixed %s" % kind)
+    out = api.filter_ragged(to_dev(flat), MIXED, mask)
+    print("worst relL2 %.3e" % _check(to_host(out), imgs, MIXED, kind))
+
+
+def test_ragged_complex_in_real_out():
+    from paper_cs_0103001_amd import api
+    sizes = [64, 16, 256, 2, 128]
+    imgs, flat = _images(sizes, seed0=200, complex_input=True)
+    announce("ragged complex in")
+    out = to_host(api.filter_ragged(to_dev(flat), sizes, dict(kind="gaussian", sigma_f=SIGMA_F)))
+    _check(out, imgs, sizes)
+    announce("ragged real out")
+    imgs_r, flat_r = _images(sizes, seed0=300)
+    outr = to_host(api.filter_ragged(to_dev(flat_r), sizes, dict(kind="gaussian", sigma_f=SIGMA_F),
+                                     real_output=True))
+    for g, im, s in zip(_split(outr, sizes), imgs_r, sizes):
+        ref = oracle.filter2(im, oracle.mask_gaussian(s, s, SIGMA_F), threads=4).real
+        assert rel_l2(g, ref, 2) < TOL
+
+
+def test_ragged_graph_replays_match_eager():
+    """The captured graph, replayed several times with other work and
+    synchronisations in between, gives the eager launches' bits every time;
+    a call with another output buffer captures again."""
+    import torch
+    from paper_cs_0103001_amd import _binding as B
+    import ctypes
+    sizes = [128, 2048, 64, 512, 256, 1024, 64]
+    imgs, flat = _images(sizes, seed0=400)
+    x = to_dev(flat)
+    mk = B.make_mask("gaussian", sigma_f=SIGMA_F)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    outs = []
+    for graph in ("0", "1"):
+        os.environ["FFTMI_RAGGED_GRAPH"] = graph
+        try:
+            h = B.fft_plan_ragged(sizes, B.FFT_IN_REAL_F32)
+        finally:
+            os.environ.pop("FFTMI_RAGGED_GRAPH", None)
+        ws = torch.empty(B.fft_workspace_size(h), dtype=torch.uint8, device="cuda")
+        for rep in range(3):
+            out = torch.full((x.numel(),), float("nan"), dtype=torch.complex64, device="cuda")
+            if rep == 2:
+                out2 = torch.empty_like(out)
+                B.fft2d_filter_ragged(h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out2.data_ptr()), mk,
+                                      ctypes.c_void_p(ws.data_ptr()), st)
+                outs.append(to_host(out2))
+            announce("ragged graph=%s rep %d" % (graph, rep))
+            B.fft2d_filter_ragged(h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), mk,
+                                  ctypes.c_void_p(ws.data_ptr()), st)
+            torch.cuda.synchronize()
+            _ = (torch.ones(1 << 20, device="cuda") * 3).sum().item()  # eager work between replays
+            outs.append(to_host(out))
+        B.fft_plan_destroy(h)
+    _check(outs[0], imgs, sizes)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_ragged_autotune_keeps_results():
+    from paper_cs_0103001_amd import api
+    sizes = [2048, 64, 64, 128, 1024, 256, 512, 64]
+    imgs, flat = _images(sizes, seed0=500)
+    x = to_dev(flat)
+    mask = dict(kind="gaussian", sigma_f=SIGMA_F)
+    announce("ragged tune")
+    sched = api.tune_ragged(x, sizes, mask)
+    print("schedule", sched)
+    assert sched["block"] in (256, 512) and sched["wg_cap"] in (0, 2)
+    assert sched["chunk_bytes"] in (0, 128 << 20)
+    _check(to_host(api.filter_ragged(x, sizes, mask)), imgs, sizes)
+
+
+def test_ragged_workload_512_sampled():
+    """The 512-image workload (sides uniform from {64..2048}, seed 3) at full
+    size: every image finite and two runs bit-identical; two images of each
+    side against the oracle."""
+    from paper_cs_0103001_amd import api
+    sizes = synth.ragged_sizes()
+    announce("ragged 512: generating %d images" % len(sizes))
+    flat = synth.ragged_batch(sizes, workers=min(16, os.cpu_count() or 1))
+    x = to_dev(flat)
+    mask = dict(kind="gaussian", sigma_f=SIGMA_F)
+    announce("ragged 512: filter")
+    out1 = api.filter_ragged(x, sizes, mask)
+    out2 = api.filter_ragged(x, sizes, mask)
+    a, b = to_host(out1), to_host(out2)
+    assert np.isfinite(a.view(np.float32)).all()
+    assert np.array_equal(a, b)
+    offs = np.concatenate([[0], np.cumsum([s * s for s in sizes])])
+    picked = []
+    for side in sorted(set(sizes)):
+        idx = [i for i, s in enumerate(sizes) if s == side][:2]
+        picked += idx
+    for i in picked:
+        s = sizes[i]
+        im = flat[offs[i]:offs[i + 1]].reshape(s, s)
+        ref = oracle.filter2(im, oracle.mask_gaussian(s, s, SIGMA_F), threads=8)
+        err = rel_l2(a[offs[i]:offs[i + 1]].reshape(s, s), ref, 2)
+        assert err < TOL, (i, s, err)
