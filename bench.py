@@ -6,9 +6,10 @@ rows) -> column FFT, Butterworth mask, inverse column FFT -> inverse row FFT
 -> complex64 image (Section 6).  `value` is GB/s under the three-pass byte
 model (44 B per pixel: read f32 4 + write c64 8, read 8 + write 8, read 8 +
 write 8), inputs resident in HBM.  Also reported: per-pass kernel times inside
-the chained step (the roofline entry is the slowest pass), a cold-cache variant, the batch-of-8
-form, the forward+backward learnable-mask form (batch 64 of 1024x1024), and
-the FP64 CPU oracle timed on this host.
+the chained step (the roofline entry is the slowest pass), a cold-cache
+variant, the batch-of-8 form, the forward+backward learnable-mask form (batch
+64 of 1024x1024), the 512-image ragged batch (graph replay after autotuning),
+and the FP64 CPU oracle timed on this host.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--skip-extra]
 """
@@ -266,6 +267,32 @@ def main():
         result["batched"]["ns_per_px"] = round(msb * 1e6 / (Bn * px), 4)
         result["batched"]["ns_per_px_plain_4096"] = round(ms * 1e6 / px, 4)
         del noisy, clean, ol, wsl
+
+    if not args.skip_extra:
+        # ------------------------------------------------------------- ragged
+        sizes = synth.ragged_sizes()
+        log("generating the ragged batch (%d images)" % len(sizes))
+        flat = synth.ragged_batch(sizes, workers=min(16, os.cpu_count() or 1))
+        xr = torch.from_numpy(flat).to(dev)
+        del flat
+        rmask = dict(synth.CONFIGS["ragged_512"]["mask"])
+        sched = api.tune_ragged(xr, sizes, rmask)
+        rplan = api.get_plan(0, (), len(sizes), B.FFT_IN_REAL_F32, dev, ragged_sizes=sizes)
+        outr = torch.empty(xr.numel(), dtype=torch.complex64, device=dev)
+        wsr = rplan.workspace()
+        rmk = B.make_mask(**rmask)
+        rp = [ctypes.c_void_p(t.data_ptr()) for t in (xr, outr, wsr)]
+        Kr = max(5, K // 5)
+        ms_r = timed(torch, lambda: B.fft2d_filter_ragged(rplan.h, rp[0], rp[1], rmk, rp[2], st), Kr, 2)
+        pxr = sum(s_ * s_ for s_ in sizes)
+        gbs_r = 44 * pxr / (ms_r * 1e-3) / 1e9
+        result["ragged"] = {"workload": "ragged_512: 512 star fields, sides uniform from {64..2048} (seed 3), "
+                                        "Gaussian sigma_f 0.1, f32 in, c64 out",
+                            "Mpx": round(pxr / 1e6, 2), "ms_per_step": round(ms_r, 4), "GB/s": round(gbs_r, 1),
+                            "hbm_frac": round(gbs_r / HBM_PEAK_GBS, 4), "images_per_s": round(512 / (ms_r * 1e-3), 1),
+                            "ns_per_px": round(ms_r * 1e6 / pxr, 4), "ns_per_px_plain_4096": round(ms * 1e6 / px, 4),
+                            "schedule": sched, "launch": "hipGraph replay (3 persistent launches per run)"}
+        del xr, outr, wsr
 
     # ---------------------------------------------------------- CPU oracle
     if not args.no_cpu:
