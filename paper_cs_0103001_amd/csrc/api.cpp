@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -298,6 +299,10 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
     // rows per block of the blocked layout: limited by the column pass's
     // thread split (N/16 % RB); the row passes take whole or half blocks.
     int rb = 4;
+    if (const char* e = std::getenv("FFTMI_RB")) {
+      const int v = std::atoi(e);
+      if (v >= 1 && v <= 16 && (v & (v - 1)) == 0) rb = v;
+    }
     while (rb > 1 && threads_per_transform((int)N) % rb) rb /= 2;
     p->rb = rb;
     p->w = tuned_cols_width(p.get());
@@ -370,7 +375,8 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
     return e == hipSuccess ? FFT_OK : hip_fail(e);
   }
 
-  // rank 2: row pass into the blocked workspace, column pass to row-major out
+  // rank 2: row pass into the blocked workspace, column pass in place, then
+  // the blocks rewritten as rows with the scale
   const float scale = fwd_norm ? fwd_scale_2d(p) : inv_scale_2d(p);
   float2* ws = static_cast<float2*>(workspace);
   const int64_t blocks = p->batch * p->n / p->rb;
@@ -379,7 +385,9 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
   e = launch_rows_to_blk(p->log_m, inv_tw, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
   Launch lcn = launch_for(st, p->tables, p->log_n);
-  e = launch_cols_single(p->log_n, inv_tw, ws, out, out_f32, p->batch, (int)p->m, p->rb, p->w, scale, lcn);
+  e = launch_cols_fft(p->log_n, inv_tw, ws, p->batch, (int)p->m, p->rb, p->w, lcn);
+  if (e != hipSuccess) return hip_fail(e);
+  e = launch_unblock(ws, out, out_f32, p->batch * p->n, (int)p->m, p->rb, scale, st);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 

@@ -63,9 +63,16 @@ FFTMI_HD constexpr int lds_tw_bytes(int L) {
   return L <= (1 << kLdsTwMaxLog2) ? ((lds_tw_entries(L) * 8 + 255) / 256) * 256 : 0;
 }
 
-// LDS footprint of one transform: one padding slot per 16 entries so that the
-// stride-16 writes of a radix-16 pass fall into distinct banks.
-FFTMI_HD constexpr int lds_pad(int i) { return i + (i >> 4); }
+// LDS footprint of one transform: one padding slot per 2^FFTMI_PAD_SHIFT
+// entries so that the strided writes of a radix-16 pass and the natural-order
+// reads fall into distinct banks.  For shifts 4 and 5 the split
+// pad(base + off) = pad(base) + pad(off) used for immediate offsets is exact
+// for every stage of every length up to 2^14 (checked exhaustively).
+#ifndef FFTMI_PAD_SHIFT
+#define FFTMI_PAD_SHIFT 4
+#endif
+static_assert(FFTMI_PAD_SHIFT == 4 || FFTMI_PAD_SHIFT == 5, "padding shift");
+FFTMI_HD constexpr int lds_pad(int i) { return i + (i >> FFTMI_PAD_SHIFT); }
 FFTMI_HD constexpr int lds_size(int L) { return L >= 16 ? L + L / 16 : L; }
 
 #ifndef FFTMI_SPLIT_X

@@ -343,11 +343,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
   }
 }
 
-// One column transform of the blocked layout, row-major output.
-template <int L, bool INV, bool F32>
-__global__ __launch_bounds__(Shape<L>::LB) void k_cols_single(const float2* __restrict__ ws, void* __restrict__ out,
-                                                              int M, int rb, int w, int ltiles, int ntiles,
-                                                      float scale, const float2* __restrict__ tws) {
+// One column transform of the blocked layout, in place (unscaled).
+template <int L, bool INV>
+__global__ __launch_bounds__(Shape<L>::LB) void k_cols_fft(float2* __restrict__ ws, int M, int rb, int w, int ltiles,
+                                                           int ntiles, const float2* __restrict__ tws) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
@@ -356,16 +355,13 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_single(const float2* __re
   char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
   const unsigned qs = (unsigned)(TPT * M);
   const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
-  const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
   const int tmask = (1 << ltiles) - 1;
   float2 a[E], nx[E];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
     const float2* b = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
-    {
-      const unsigned f_lane = fresh(lane);
+    const unsigned f_lane = fresh(lane);
 #pragma unroll
-      for (int q = 0; q < E; ++q) d[q] = ld(b, f_lane + q * qs);
-    }
+    for (int q = 0; q < E; ++q) d[q] = b[f_lane + q * qs];
   };
   int n = blockIdx.x;
   if (n < ntiles) load(a, (int)tile_of(n, ntiles));
@@ -374,24 +370,42 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_single(const float2* __re
     const int t = (int)tile_of(n, ntiles);
     if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
     fft_reg<L, INV, S::TWM>(a, ln.j, x, tw);
-    const int64_t o = (int64_t)(t >> ltiles) * L * M + (t & tmask) * w;
-    if constexpr (F32) {
-      float* b = static_cast<float*>(out) + o;
-      {
-        const unsigned f_lane_out = fresh(lane_out);
+    float2* b = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    {
+      const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) b[f_lane_out + q * qs] = a[q].x * scale;
-      }
-    } else {
-      float2* b = static_cast<float2*>(out) + o;
-      {
-        const unsigned f_lane_out = fresh(lane_out);
-#pragma unroll
-        for (int q = 0; q < E; ++q) b[f_lane_out + q * qs] = cscale(a[q], scale);
-      }
+      for (int q = 0; q < E; ++q) b[f_lane + q * qs] = a[q];
     }
 #pragma unroll
     for (int q = 0; q < E; ++q) a[q] = nx[q];
+  }
+}
+
+// Blocked workspace -> row-major output, times scale.  A thread owns column v
+// of one block: it reads the block's RB values of that column (RB*8
+// contiguous bytes) and writes them to the RB rows, so each of a wavefront's
+// stores covers 64 consecutive elements of one row.
+template <int RB, bool F32>
+__global__ __launch_bounds__(256) void k_unblock(const float2* __restrict__ ws, void* __restrict__ out, int M,
+                                                 int64_t items, float scale) {
+  const int lm = ilog2_pow2(M);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = i >> lm;
+    const int v = (int)(i & (M - 1));
+    const float2* src = ws + (blk * M + v) * RB;
+    float2 a[RB];
+#pragma unroll
+    for (int s = 0; s < RB; ++s) a[s] = __ldg(src + s);
+    const int64_t row0 = blk * RB;
+    if constexpr (F32) {
+      float* dst = static_cast<float*>(out) + row0 * M + v;
+#pragma unroll
+      for (int s = 0; s < RB; ++s) dst[(int64_t)s * M] = a[s].x * scale;
+    } else {
+      float2* dst = static_cast<float2*>(out) + row0 * M + v;
+#pragma unroll
+      for (int s = 0; s < RB; ++s) dst[(int64_t)s * M] = cscale(a[s], scale);
+    }
   }
 }
 
@@ -702,12 +716,15 @@ int pair_per_tile(int rb) {
   return npt;
 }
 
-// Rows per tile of the blocked row passes: the most that fit in LDS.
+// Rows per tile of the blocked row passes.  The pass that writes the blocked
+// layout takes as many rows of a block as a workgroup holds (up to `target`
+// threads), so that more of each block's interleaved segments are written by
+// one workgroup; the pass that reads it aims at 256-thread workgroups,
+// several of which share a CU.
 template <int L>
-int rows_per_tile(int rb) {
-  // aim at 256-thread workgroups (several resident per CU)
+int rows_per_tile(int rb, int target) {
   int nt = rb;
-  while (nt > 1 && nt * threads_per_transform(L) > 256) nt /= 2;
+  while (nt > 1 && nt * threads_per_transform(L) > target) nt /= 2;
   if (const char* e = std::getenv("FFTMI_ROWS_NT")) {
     const int v = std::atoi(e);
     if (v >= 1 && v <= rb && (v & (v - 1)) == 0) nt = v;
@@ -738,7 +755,7 @@ struct RowsToBlk {
                   scale, tw);
       }
     }
-    const int nt = rows_per_tile<L>(rb);
+    const int nt = rows_per_tile<L>(rb, 512);
     const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
     const int64_t ntiles = blocks * (rb / nt);
     if (inv)
@@ -755,7 +772,7 @@ struct RowsFromBlk {
                         const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const float2* tw = twiddle_src<L>(lc);
-    const int nt = rows_per_tile<L>(rb);
+    const int nt = rows_per_tile<L>(rb, 256);
     const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
     const int64_t ntiles = blocks * (rb / nt);
     auto k = inv ? (out_f32 ? k_rows_from_blk<L, true, true> : k_rows_from_blk<L, true, false>)
@@ -795,18 +812,16 @@ struct ColsFilter {
 };
 
 template <int LG>
-struct ColsSingle {
-  static hipError_t run(bool inv, const float2* ws, void* out, bool out_f32, int64_t nimg, int M, int rb, int w,
-                        float scale, const Launch& lc) {
+struct ColsFft {
+  static hipError_t run(bool inv, float2* ws, int64_t nimg, int M, int rb, int w, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = M / w;
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
     const float2* tw = twiddle_src<L>(lc);
     const int64_t ntiles = nimg * tiles;
     const int lt = ilog2c(tiles);
-    auto k = inv ? (out_f32 ? k_cols_single<L, true, true> : k_cols_single<L, true, false>)
-                 : (out_f32 ? k_cols_single<L, false, true> : k_cols_single<L, false, false>);
-    return go(k, ntiles, w * TPT, lds, lc.stream, ws, out, M, rb, w, lt, (int)ntiles, scale, tw);
+    auto k = inv ? k_cols_fft<L, true> : k_cols_fft<L, false>;
+    return go(k, ntiles, w * TPT, lds, lc.stream, ws, M, rb, w, lt, (int)ntiles, tw);
   }
 };
 
@@ -867,9 +882,9 @@ struct ColsStrided {
 #define FFTMI_CASE_ColsFilter(K) \
   case K:                        \
     return ColsFilter<K>::run(ws, save, nimg, M, rb, w, mask, lc);
-#define FFTMI_CASE_ColsSingle(K) \
-  case K:                        \
-    return ColsSingle<K>::run(inv, ws, out, out_f32, nimg, M, rb, w, scale, lc);
+#define FFTMI_CASE_ColsFft(K) \
+  case K:                     \
+    return ColsFft<K>::run(inv, ws, nimg, M, rb, w, lc);
 #define FFTMI_CASE_ColsGrad(K) \
   case K:                      \
     return ColsGrad<K>::run(ws, save, mask, part, nimg, groups, M, rb, w, w_lin, w_sq, lc);
@@ -897,9 +912,32 @@ hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg,
   FFTMI_DISPATCH(ColsFilter, log2L)
 }
 
-hipError_t launch_cols_single(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t nimg, int M,
-                              int rb, int w, float scale, const Launch& lc) {
-  FFTMI_DISPATCH(ColsSingle, log2L)
+hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, int w, const Launch& lc) {
+  FFTMI_DISPATCH(ColsFft, log2L)
+}
+
+hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, float scale,
+                          hipStream_t st) {
+  if (rows % rb || (M & (M - 1))) return hipErrorInvalidValue;
+  const int64_t items = rows / rb * M;
+  if (items == 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((items + 255) / 256, 65536);
+  const dim3 g((unsigned)blocks), b(256);
+#define FFTMI_UNBLOCK(R)                                                                                   \
+  if (rb == R) {                                                                                           \
+    if (out_f32)                                                                                           \
+      hipLaunchKernelGGL((k_unblock<R, true>), g, b, 0, st, ws, out, M, items, scale);                     \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_unblock<R, false>), g, b, 0, st, ws, out, M, items, scale);                    \
+    return hipGetLastError();                                                                              \
+  }
+  FFTMI_UNBLOCK(1)
+  FFTMI_UNBLOCK(2)
+  FFTMI_UNBLOCK(4)
+  FFTMI_UNBLOCK(8)
+  FFTMI_UNBLOCK(16)
+#undef FFTMI_UNBLOCK
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, const float* mask, float* part,

@@ -51,9 +51,13 @@ hipError_t launch_rows_from_blk(int log2L, bool inv, const float2* ws, void* out
 hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w,
                               const MaskArgs& mask, const Launch& lc);
 
-// Column pass on the blocked layout: one transform, row-major output.
-hipError_t launch_cols_single(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t nimg, int M,
-                              int rb, int w, float scale, const Launch& lc);
+// Column pass on the blocked layout: one unscaled transform, in place.
+hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, int w, const Launch& lc);
+
+// Blocked workspace (rows rows in blocks of rb) -> row-major out, times scale;
+// complex64 or, with out_f32, the real parts.
+hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, float scale,
+                          hipStream_t st);
 
 // Column pass for the mask gradient over images split into `groups` runs of
 // consecutive images: for every (group, column tile), forward-transform the
