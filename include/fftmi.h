@@ -113,6 +113,25 @@ int fft_exec(fft_plan_t plan, const void* in, void* out, void* workspace, int di
 int fft2d_filter(fft_plan_t plan, const void* in, void* out, const fft_mask* mask, void* workspace,
                  void* stream);
 
+/* Plan for images of any size n0 x m0 = dims0[0] x dims0[1] (1 .. 16384
+ * each), filtered as Section 6 does: each axis is padded with zeros (rows
+ * appended at the bottom, columns at the right) to the next power of two,
+ * N x M, the padded image is filtered, and the result is cropped back to the
+ * first n0 rows and m0 columns.  fft2d_filter on such a plan takes in
+ * [batch][n0][m0] and writes out [batch][n0][m0] (element types from flags);
+ * masks are evaluated on the N x M frequency grid (the disc's default centre
+ * is (N/2, M/2)).  When n0 and m0 are powers of two this is fft_plan.
+ * fft_exec, fft2d_filter_stage, fft2d_filter_save and the mask gradients
+ * return FFT_ERR_UNSUPPORTED on a padded plan.  The workspace also holds the
+ * padded input and output.  Errors: FFT_ERR_ARG, FFT_ERR_SIZE, as fft_plan. */
+int fft_plan_padded(fft_plan_t* out, const int64_t* dims0, int64_t batch, uint32_t flags);
+
+/* Fourier spectrum magnitude |F[u][v]| of every image, F = 2D-DFT of the
+ * (zero-padded) image under eq. 5 (or FFT_NORM_NUMPY's unscaled transform):
+ * float32 [batch][N][M], unshifted (F[0][0] first), for a rank-2 plan from
+ * fft_plan or fft_plan_padded (Section 6 shows this spectrum of its image). */
+int fft2d_spectrum(fft_plan_t plan, const void* in, float* magnitude, void* workspace, void* stream);
+
 /* One of the three passes of fft2d_filter, for callers that schedule (or
  * time) the passes themselves; running stages 0, 1, 2 in order on one stream
  * with the same workspace is fft2d_filter.

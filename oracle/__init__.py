@@ -166,6 +166,37 @@ def filter2(f, mask, threads: int = None) -> np.ndarray:
     return out
 
 
+# ------------------------------------------------- Section 6 padding/cropping
+def next_pow2(n: int) -> int:
+    """Smallest power of two >= n (Section 6 pads each axis to such a length)."""
+    p = 1
+    while p < n:
+        p <<= 1
+    return p
+
+
+def pad2(f) -> np.ndarray:
+    """Zero padding of the last two axes (n0 x m0) to the next powers of two,
+    the added rows at the bottom and columns at the right (Section 6)."""
+    f = np.asarray(f)
+    n0, m0 = f.shape[-2], f.shape[-1]
+    widths = [(0, 0)] * (f.ndim - 2) + [(0, next_pow2(n0) - n0), (0, next_pow2(m0) - m0)]
+    return np.pad(f, widths)
+
+
+def filter2_padded(f, mask, threads: int = None) -> np.ndarray:
+    """Section 6 on an image of any size: pad to powers of two, filter with the
+    real mask given for the padded N x M grid, crop back to n0 x m0."""
+    f = np.asarray(f)
+    n0, m0 = f.shape[-2], f.shape[-1]
+    return filter2(pad2(f), mask, threads)[..., :n0, :m0]
+
+
+def spectrum_padded(f, threads: int = None) -> np.ndarray:
+    """|2D-DFT| (eq. 5) of the zero-padded image, unshifted (Section 6's spectrum)."""
+    return np.abs(fft2(pad2(f), threads))
+
+
 # ------------------------------------------------------------------------ masks
 def mask_gaussian(N: int, M: int, sigma_f: float) -> np.ndarray:
     """exp(-r^2 / (2 sigma_f^2)), r in cycles/pixel on the fftfreq grid."""

@@ -70,6 +70,8 @@ _SIGS = {
     "fft_plan_tune": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
     "fft_plan_schedule": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                          _I64P, ctypes.POINTER(ctypes.c_int)]),
+    "fft_plan_padded": (ctypes.c_int, [ctypes.POINTER(_P), _I64P, ctypes.c_int64, ctypes.c_uint32]),
+    "fft2d_spectrum": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "fft_plan_destroy": (ctypes.c_int, [_P]),
     "fft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fft_version": (ctypes.c_int, []),
@@ -118,6 +120,16 @@ def fft_plan(rank, dims, batch, flags=0):
     h = _P()
     check(lib().fft_plan(ctypes.byref(h), int(rank), _dims(dims), int(batch), int(flags)), "fft_plan")
     return h
+
+
+def fft_plan_padded(dims0, batch, flags=0):
+    h = _P()
+    check(lib().fft_plan_padded(ctypes.byref(h), _dims(dims0), int(batch), int(flags)), "fft_plan_padded")
+    return h
+
+
+def fft2d_spectrum(plan, inp, magnitude, workspace, stream):
+    check(lib().fft2d_spectrum(plan, inp, magnitude, workspace, stream), "fft2d_spectrum")
 
 
 def fft_plan_ragged(sizes, flags=0):

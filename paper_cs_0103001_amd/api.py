@@ -19,16 +19,19 @@ _NORM = {"paper": B.FFT_NORM_PAPER, "numpy": B.FFT_NORM_NUMPY}
 class Plan:
     """Owns one fft_plan_t (created on the tensor's device)."""
 
-    def __init__(self, rank, dims, batch, flags=0, device=None, ragged_sizes=None):
+    def __init__(self, rank, dims, batch, flags=0, device=None, ragged_sizes=None, padded=False):
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device.index)
         with torch.cuda.device(self.device):
             if ragged_sizes is not None:
                 self.h = B.fft_plan_ragged(ragged_sizes, flags)
+            elif padded:
+                self.h = B.fft_plan_padded(dims, batch, flags)
             else:
                 self.h = B.fft_plan(rank, dims, batch, flags)
         self.rank, self.dims, self.batch, self.flags = rank, tuple(dims), batch, flags
         self.workspace_bytes = B.fft_workspace_size(self.h)
         self.spectrum_bytes = B.fft_spectrum_size(self.h) if rank == 2 and ragged_sizes is None else 0
+        self.padded = padded
 
     def workspace(self):
         n = max(self.workspace_bytes, 1)
@@ -48,13 +51,13 @@ _cache = {}
 _cache_lock = threading.Lock()
 
 
-def get_plan(rank, dims, batch, flags, device, ragged_sizes=None):
+def get_plan(rank, dims, batch, flags, device, ragged_sizes=None, padded=False):
     key = (rank, tuple(dims), int(batch), int(flags), device.index,
-           tuple(ragged_sizes) if ragged_sizes is not None else None)
+           tuple(ragged_sizes) if ragged_sizes is not None else None, bool(padded))
     with _cache_lock:
         p = _cache.get(key)
         if p is None:
-            p = Plan(rank, dims, batch, flags, device, ragged_sizes)
+            p = Plan(rank, dims, batch, flags, device, ragged_sizes, padded)
             _cache[key] = p
     return p
 
@@ -146,9 +149,12 @@ def fft2d_filter(x, mask, norm="paper", real_output=False, spectrum=False):
     N, M = x.shape[-2], x.shape[-1]
     batch = x.numel() // (N * M) if N * M else 0
     flags = fin | _NORM[norm] | (B.FFT_OUT_REAL_F32 if real_output else 0)
-    plan = get_plan(2, (N, M), batch, flags, x.device)
+    padded = not (_pow2(N) and _pow2(M))
+    if padded and spectrum:
+        raise ValueError("the saved spectrum needs power-of-two sides")
+    plan = get_plan(2, (N, M), batch, flags, x.device, padded=padded)
     out = torch.empty(x.shape, dtype=torch.float32 if real_output else torch.complex64, device=x.device)
-    mk, keep = _mask_struct(mask, N, M, x.device)
+    mk, keep = _mask_struct(mask, _next_pow2(N), _next_pow2(M), x.device)
     ws = plan.workspace()
     st = _stream(x.device)
     if spectrum:
@@ -159,6 +165,32 @@ def fft2d_filter(x, mask, norm="paper", real_output=False, spectrum=False):
     if batch:
         B.fft2d_filter(plan.h, _ptr(x), _ptr(out), mk, _ptr(ws), st)
     del keep
+    return out
+
+
+def _pow2(n):
+    return n > 0 and (n & (n - 1)) == 0
+
+
+def _next_pow2(n):
+    p = 1
+    while p < n:
+        p <<= 1
+    return p
+
+
+def spectrum(x, norm="paper"):
+    """|2D-DFT| (eq. 5) over the last two axes, zero-padded to powers of two
+    as in Section 6: float32 [..., N, M] with N, M the padded sides, unshifted."""
+    x, fin = _prep(x)
+    n0, m0 = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (n0 * m0) if n0 * m0 else 0
+    N, M = _next_pow2(n0), _next_pow2(m0)
+    plan = get_plan(2, (n0, m0), batch, fin | _NORM[norm], x.device, padded=not (N == n0 and M == m0))
+    out = torch.empty(tuple(x.shape[:-2]) + (N, M), dtype=torch.float32, device=x.device)
+    if batch:
+        ws = plan.workspace()
+        B.fft2d_spectrum(plan.h, _ptr(x), _ptr(out), _ptr(ws), _stream(x.device))
     return out
 
 

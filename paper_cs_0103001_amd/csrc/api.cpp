@@ -321,6 +321,64 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
   return FFT_OK;
 }
 
+int fft_plan_padded(fft_plan_t* out, const int64_t* dims0, int64_t batch, uint32_t flags) {
+  if (!out) return FFT_ERR_ARG;
+  *out = nullptr;
+  if (!dims0 || batch < 0) return FFT_ERR_ARG;
+  const int64_t n0 = dims0[0], m0 = dims0[1];
+  if (n0 < 1 || m0 < 1 || n0 > (1 << kMaxLog2Row) || m0 > (1 << kMaxLog2Row)) return FFT_ERR_SIZE;
+  int64_t N = 1, M = 1;
+  while (N < n0) N <<= 1;
+  while (M < m0) M <<= 1;
+  const int64_t dims[2] = {N, M};
+  fft_plan_t p = nullptr;
+  int rc = fft_plan(&p, 2, dims, batch, flags);
+  if (rc != FFT_OK) return rc;
+  if (N != n0 || M != m0) {
+    p->padded = true;
+    p->n0 = n0;
+    p->m0 = m0;
+    const size_t plane = (size_t)batch * (size_t)N * (size_t)M;
+    const size_t in_bytes = plane * ((flags & FFT_IN_REAL_F32) ? sizeof(float) : sizeof(float2));
+    const size_t out_bytes = plane * ((flags & FFT_OUT_REAL_F32) ? sizeof(float) : sizeof(float2));
+    p->pad_in_off = (p->ws_bytes + 255) & ~(size_t)255;
+    p->pad_out_off = (p->pad_in_off + in_bytes + 255) & ~(size_t)255;
+    p->ws_bytes = p->pad_out_off + out_bytes;
+  }
+  *out = p;
+  return FFT_OK;
+}
+
+int fft2d_spectrum(fft_plan_t p, const void* in, float* magnitude, void* workspace, void* stream) {
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  if (p->kind != 2) return FFT_ERR_STATE;
+  if (p->batch == 0) return FFT_OK;
+  if (!in || !magnitude) return FFT_ERR_ARG;
+  if (!workspace) return FFT_ERR_WORKSPACE;
+  int rc = check_plan(p, nullptr);
+  if (rc != FFT_OK) return rc;
+  const bool in_f32 = p->flags & FFT_IN_REAL_F32;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  float2* ws = static_cast<float2*>(workspace);
+  hipError_t e;
+  if (p->padded) {
+    char* wsb = static_cast<char*>(workspace);
+    e = launch_pad(in, wsb + p->pad_in_off, in_f32, p->batch, (int)p->n0, (int)p->m0, p->log_n, p->log_m, st);
+    if (e != hipSuccess) return hip_fail(e);
+    in = wsb + p->pad_in_off;
+  }
+  const int64_t blocks = p->batch * p->n / p->rb;
+  const bool pair = in_f32 && p->rb >= 2;
+  Launch lr = launch_for(st, p->tables, p->log_m);
+  e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
+  if (e != hipSuccess) return hip_fail(e);
+  Launch lcn = launch_for(st, p->tables, p->log_n);
+  e = launch_cols_fft(p->log_n, false, ws, p->batch, (int)p->m, p->rb, p->w, lcn);
+  if (e != hipSuccess) return hip_fail(e);
+  e = launch_unblock_mag(ws, magnitude, p->batch * p->n, (int)p->m, p->rb, fwd_scale_2d(p), st);
+  return e == hipSuccess ? FFT_OK : hip_fail(e);
+}
+
 int fft_workspace_size(fft_plan_t plan, size_t* bytes) {
   if (!plan_live(plan) || !bytes) return FFT_ERR_ARG;
   *bytes = plan->ws_bytes;
@@ -340,6 +398,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
       direction != FFT_ADJ_INVERSE)
     return FFT_ERR_ARG;
   if (p->kind != 1 && p->kind != 2) return FFT_ERR_STATE;
+  if (p->padded) return FFT_ERR_UNSUPPORTED;
   if (p->batch == 0) return FFT_OK;
   if (!in || !out || in == out) return FFT_ERR_ARG;
   if (p->ws_bytes && !workspace) return FFT_ERR_WORKSPACE;
@@ -410,6 +469,18 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   const bool pair = in_f32 && p->rb >= 2;
   Launch lr = launch_for(st, p->tables, p->log_m);
   Launch lcn = launch_for(st, p->tables, p->log_n);
+  // Section 6's padding: the caller's n0 x m0 images are zero-padded into
+  // the workspace, filtered there, and the result cropped back into `out`.
+  void* final_out = out;
+  if (p->padded) {
+    if (stages != 7 || spectrum) return FFT_ERR_UNSUPPORTED;
+    char* wsb = static_cast<char*>(workspace);
+    hipError_t e = launch_pad(in, wsb + p->pad_in_off, in_f32, p->batch, (int)p->n0, (int)p->m0, p->log_n, p->log_m,
+                              st);
+    if (e != hipSuccess) return hip_fail(e);
+    in = wsb + p->pad_in_off;
+    out = wsb + p->pad_out_off;
+  }
   // The whole filter runs chunk by chunk: the three passes over one chunk of
   // images before the next, with the chunk's intermediate small enough to
   // stay in the memory-side cache between the passes.  A single stage covers
@@ -435,6 +506,10 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
       e = launch_rows_from_blk(p->log_m, true, ws, cout, out_f32, blocks, p->rb, inv_scale_2d(p), lr);
       if (e != hipSuccess) return hip_fail(e);
     }
+  }
+  if (p->padded) {
+    hipError_t e = launch_crop(out, final_out, out_f32, p->batch, (int)p->n0, (int)p->m0, p->log_n, p->log_m, st);
+    if (e != hipSuccess) return hip_fail(e);
   }
   return FFT_OK;
 }
@@ -463,6 +538,7 @@ static int grad_impl(fftmi_plan* p, const void* in, const void* spectrum, const 
                      float* grad_mask, void* workspace, void* stream) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
+  if (p->padded) return FFT_ERR_UNSUPPORTED;
   if (!grad_mask) return FFT_ERR_ARG;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->batch == 0) {

@@ -409,6 +409,50 @@ __global__ __launch_bounds__(256) void k_unblock(const float2* __restrict__ ws, 
   }
 }
 
+// Section 6 front end: zero padding of [B][n0][m0] images to [B][N][M]
+// (appended rows and columns), and cropping back.  Element-wise, coalesced.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pad(const T* __restrict__ in, T* __restrict__ out, int64_t total, int n0,
+                                             int m0, int lN, int lM) {
+  const int64_t N = int64_t(1) << lN, M = int64_t(1) << lM;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i >> (lN + lM);
+    const int u = (int)((i >> lM) & (N - 1)), v = (int)(i & (M - 1));
+    out[i] = (u < n0 && v < m0) ? in[(b * n0 + u) * m0 + v] : T{};
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_crop(const T* __restrict__ in, T* __restrict__ out, int64_t total, int n0,
+                                              int m0, int lN, int lM) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t bu = i / m0;
+    const int v = (int)(i - bu * m0);
+    const int64_t b = bu / n0;
+    const int u = (int)(bu - b * n0);
+    out[i] = in[((b << lN) + u) * (int64_t(1) << lM) + v];
+  }
+}
+
+// |z| * scale of the blocked workspace into row-major float32 (the spectrum
+// magnitude), laid out like k_unblock's output.
+template <int RB>
+__global__ __launch_bounds__(256) void k_unblock_mag(const float2* __restrict__ ws, float* __restrict__ out, int M,
+                                                     int64_t items, float scale) {
+  const int lm = ilog2_pow2(M);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t blk = i >> lm;
+    const int v = (int)(i & (M - 1));
+    const float2* src = ws + (blk * M + v) * RB;
+    float* dst = out + blk * RB * M + v;
+#pragma unroll
+    for (int s = 0; s < RB; ++s) {
+      const float2 z = __ldg(src + s);
+      dst[(int64_t)s * M] = sqrtf(fmaf(z.x, z.x, z.y * z.y)) * scale;
+    }
+  }
+}
+
 // Mask gradient.  A tile is (image group g, column tile): loop over the
 // group's images in order, forward-transform the blocked rows of the incoming
 // gradient (or residual), multiply by conj(saved spectrum X) and accumulate
@@ -914,6 +958,63 @@ hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg,
 
 hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, int w, const Launch& lc) {
   FFTMI_DISPATCH(ColsFft, log2L)
+}
+
+namespace {
+dim3 elementwise_grid(int64_t n) { return dim3((unsigned)std::min<int64_t>((n + 255) / 256, 65536)); }
+}  // namespace
+
+hipError_t launch_pad(const void* in, void* out, bool f32, int64_t nimg, int n0, int m0, int log2N, int log2M,
+                      hipStream_t st) {
+  const int64_t total = nimg << (log2N + log2M);
+  if (total == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_pad<float>, elementwise_grid(total), dim3(256), 0, st, static_cast<const float*>(in),
+                       static_cast<float*>(out), total, n0, m0, log2N, log2M);
+  else
+    hipLaunchKernelGGL(k_pad<float2>, elementwise_grid(total), dim3(256), 0, st, static_cast<const float2*>(in),
+                       static_cast<float2*>(out), total, n0, m0, log2N, log2M);
+  return hipGetLastError();
+}
+
+hipError_t launch_crop(const void* in, void* out, bool f32, int64_t nimg, int n0, int m0, int log2N, int log2M,
+                       hipStream_t st) {
+  const int64_t total = nimg * n0 * m0;
+  if (total == 0) return hipSuccess;
+  if (f32)
+    hipLaunchKernelGGL(k_crop<float>, elementwise_grid(total), dim3(256), 0, st, static_cast<const float*>(in),
+                       static_cast<float*>(out), total, n0, m0, log2N, log2M);
+  else
+    hipLaunchKernelGGL(k_crop<float2>, elementwise_grid(total), dim3(256), 0, st, static_cast<const float2*>(in),
+                       static_cast<float2*>(out), total, n0, m0, log2N, log2M);
+  return hipGetLastError();
+}
+
+hipError_t launch_unblock_mag(const float2* ws, float* out, int64_t rows, int M, int rb, float scale, hipStream_t st) {
+  if (rows % rb || (M & (M - 1))) return hipErrorInvalidValue;
+  const int64_t items = rows / rb * M;
+  if (items == 0) return hipSuccess;
+  const dim3 g = elementwise_grid(items), b(256);
+  switch (rb) {
+    case 1:
+      hipLaunchKernelGGL(k_unblock_mag<1>, g, b, 0, st, ws, out, M, items, scale);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_unblock_mag<2>, g, b, 0, st, ws, out, M, items, scale);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_unblock_mag<4>, g, b, 0, st, ws, out, M, items, scale);
+      break;
+    case 8:
+      hipLaunchKernelGGL(k_unblock_mag<8>, g, b, 0, st, ws, out, M, items, scale);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_unblock_mag<16>, g, b, 0, st, ws, out, M, items, scale);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, float scale,

@@ -59,6 +59,16 @@ hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M,
 hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, float scale,
                           hipStream_t st);
 
+// |z| * scale of the blocked workspace into row-major float32.
+hipError_t launch_unblock_mag(const float2* ws, float* out, int64_t rows, int M, int rb, float scale, hipStream_t st);
+
+// Zero padding [nimg][n0][m0] -> [nimg][2^log2N][2^log2M] and cropping back
+// (float32 or complex64 elements).
+hipError_t launch_pad(const void* in, void* out, bool f32, int64_t nimg, int n0, int m0, int log2N, int log2M,
+                      hipStream_t st);
+hipError_t launch_crop(const void* in, void* out, bool f32, int64_t nimg, int n0, int m0, int log2N, int log2M,
+                       hipStream_t st);
+
 // Column pass for the mask gradient over images split into `groups` runs of
 // consecutive images: for every (group, column tile), forward-transform the
 // blocked rows of each image in order, multiply by conj(saved spectrum X) and

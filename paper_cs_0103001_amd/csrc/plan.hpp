@@ -38,6 +38,12 @@ struct fftmi_plan {
   int rb = 1, w = 1;
   // rank 2: images per chunk of fft2d_filter (passes run chunk by chunk)
   int64_t chunk = 1;
+  // rank 2 made by fft_plan_padded: the callers' image size n0 x m0 (zero
+  // padded to n x m, the next powers of two), and the workspace offsets of
+  // the padded input and the padded (uncropped) output
+  bool padded = false;
+  int64_t n0 = 0, m0 = 0;
+  size_t pad_in_off = 0, pad_out_off = 0;
   // rank 1 beyond one LDS pass: four-step split N = N1 * N2
   bool fourstep = false;
   int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1, tw_h = 0;

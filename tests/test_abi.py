@@ -89,3 +89,19 @@ def test_mask_struct_layout_matches_header():
     assert m.kind.offset == 0 and m.data.offset == 8 and m.sigma_f.offset == 16
     assert m.cutoff.offset == 24 and m.order.offset == 32 and m.b.offset == 40
     assert m.c2.offset == 56 and ctypes.sizeof(m) == 64
+
+
+def test_padded_plan_and_spectrum_argument_errors():
+    lib = B.lib()
+    h = ctypes.c_void_p()
+    bad = (ctypes.c_int64 * 2)(0, 5)
+    assert lib.fft_plan_padded(ctypes.byref(h), bad, 1, 0) == B.FFT_ERR_SIZE
+    big = (ctypes.c_int64 * 2)(17000, 5)
+    assert lib.fft_plan_padded(ctypes.byref(h), big, 1, 0) == B.FFT_ERR_SIZE
+    ok = (ctypes.c_int64 * 2)(460, 506)
+    assert lib.fft_plan_padded(None, ok, 1, 0) == B.FFT_ERR_ARG
+    assert lib.fft_plan_padded(ctypes.byref(h), None, 1, 0) == B.FFT_ERR_ARG
+    assert lib.fft_plan_padded(ctypes.byref(h), ok, -1, 0) == B.FFT_ERR_ARG
+    p = ctypes.c_void_p(0x10)
+    assert lib.fft2d_spectrum(ctypes.c_void_p(0x1234), p, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft_plan_tune(ctypes.c_void_p(0x1234), p, p, None, p, None) == B.FFT_ERR_ARG

@@ -287,3 +287,45 @@ def test_table1_complexity_model():
         assert round(complexity.speedup(m, 2), 2) == float(rsp)
     # the worked example: N=8, nproc=4 -> m=3, m1=1
     assert complexity.parallel_products(3, 0) == complexity.sequential_products(3)
+
+
+# ------------------------------------------------- Section 6 padding/cropping
+def test_pad2_appends_zero_rows_and_columns():
+    f = np.arange(460 * 506, dtype=np.float64).reshape(460, 506)
+    g = oracle.pad2(f)
+    assert g.shape == (512, 512)
+    assert np.array_equal(g[:460, :506], f)
+    assert not g[460:, :].any() and not g[:, 506:].any()
+    h = np.ones((2, 16, 32))
+    assert np.array_equal(oracle.pad2(h), h)
+    assert [oracle.next_pow2(n) for n in (1, 2, 3, 5, 16, 17, 460)] == [1, 2, 4, 8, 16, 32, 512]
+
+
+def test_padded_filter_pins():
+    rng = np.random.default_rng(21)
+    f = rng.standard_normal((2, 13, 20))
+    N, M = 16, 32
+    # powers of two: nothing to pad, the plain filter
+    g = rng.standard_normal((16, 32))
+    m = rng.uniform(0, 1, (16, 32))
+    assert np.allclose(oracle.filter2_padded(g, m), oracle.filter2(g, m), rtol=0, atol=1e-12)
+    # an all-ones mask is the identity on the original region
+    assert np.allclose(oracle.filter2_padded(f, np.ones((N, M))), f, rtol=0, atol=1e-12)
+    # a DC-only mask gives the mean over the padded N x M array (eq. 5's 1/N,
+    # the 2D-IDFT's 1/M)
+    dc = np.zeros((N, M))
+    dc[0, 0] = 1.0
+    out = oracle.filter2_padded(f, dc)
+    for b in range(2):
+        assert np.allclose(out[b], f[b].sum() / (N * M), rtol=0, atol=1e-12)
+
+
+def test_padded_spectrum_pins():
+    rng = np.random.default_rng(22)
+    f = rng.standard_normal((11, 6))
+    S = oracle.spectrum_padded(f)
+    N, M = 16, 8
+    assert S.shape == (N, M)
+    assert abs(S[0, 0] - abs(f.sum()) / N) < 1e-12
+    # Parseval under eq. 5: sum |F|^2 = (M / N) sum |f|^2 (zeros add nothing)
+    assert abs((S ** 2).sum() - M / N * (f ** 2).sum()) < 1e-9 * (f ** 2).sum()
