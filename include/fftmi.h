@@ -65,6 +65,16 @@ extern "C" {
 #define FFT_OUT_REAL_F32 0x2u /* output keeps only the real part, float32 */
 #define FFT_NORM_PAPER 0x0u   /* the paper's scale factors, listed above (default) */
 #define FFT_NORM_NUMPY 0x4u   /* forward unscaled, inverse 1/(number of points) */
+/* Rank-2 plans for fft2d_filter on real images with masks even in
+ * frequency, H(-u, -v) = H(u, v) (Gaussian, Butterworth, none, a disc
+ * centred at 0 or N/2 by 0 or M/2): the 2D spectrum of a real image is
+ * Hermitian, so only columns 0 .. M/2 are carried (columns 0 and M/2 packed
+ * into one complex column) and the result, which is real, comes from one
+ * complex inverse transform per two rows.  Requires FFT_IN_REAL_F32, N >= 32
+ * and M >= 4; the output is float32, or complex64 with zero imaginary parts.
+ * Other masks, fft_exec, fft2d_filter_save, fft2d_spectrum and the gradients
+ * return FFT_ERR_UNSUPPORTED on such a plan. */
+#define FFT_REAL_EVEN 0x8u
 
 /* ------------------------------------------------------------------ masks */
 #define FFT_MASK_NONE 0        /* H = 1 */

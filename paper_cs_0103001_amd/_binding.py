@@ -29,6 +29,7 @@ FFT_OUT_C64 = 0x0
 FFT_OUT_REAL_F32 = 0x2
 FFT_NORM_PAPER = 0x0
 FFT_NORM_NUMPY = 0x4
+FFT_REAL_EVEN = 0x8
 
 FFT_MASK_NONE = 0
 FFT_MASK_TENSOR_F32 = 1

@@ -137,18 +137,24 @@ def _mask_struct(mask, N, M, device):
     return B.make_mask(kind, **spec), None
 
 
-def fft2d_filter(x, mask, norm="paper", real_output=False, spectrum=False):
+def fft2d_filter(x, mask, norm="paper", real_output=False, spectrum=False, real_even=False):
     """Section 6: 2D-IDFT(H . 2D-DFT(x)) over the last two axes of x.
 
     mask: dict(kind="gaussian", sigma_f=...), dict(kind="butterworth",
     cutoff=..., order=...), dict(kind="disc", b=..., c1=..., c2=...), a float32
     [N][M] tensor, or None.  With spectrum=True also returns the saved forward
-    spectrum (internal layout) used by mask_grad.
+    spectrum (internal layout) used by mask_grad.  real_even=True takes the
+    half-spectrum path (FFT_REAL_EVEN): float32 input and a mask even in
+    frequency; the output is then real (its imaginary parts are zero).
     """
     x, fin = _prep(x)
     N, M = x.shape[-2], x.shape[-1]
     batch = x.numel() // (N * M) if N * M else 0
     flags = fin | _NORM[norm] | (B.FFT_OUT_REAL_F32 if real_output else 0)
+    if real_even:
+        if fin != B.FFT_IN_REAL_F32:
+            raise TypeError("real_even needs float32 input")
+        flags |= B.FFT_REAL_EVEN
     padded = not (_pow2(N) and _pow2(M))
     if padded and spectrum:
         raise ValueError("the saved spectrum needs power-of-two sides")

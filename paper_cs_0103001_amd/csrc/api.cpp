@@ -260,8 +260,9 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
   if (!out) return FFT_ERR_ARG;
   *out = nullptr;
   if ((rank != 1 && rank != 2) || !dims || batch < 0) return FFT_ERR_ARG;
-  if (flags & ~(FFT_IN_REAL_F32 | FFT_OUT_REAL_F32 | FFT_NORM_NUMPY)) return FFT_ERR_ARG;
+  if (flags & ~(FFT_IN_REAL_F32 | FFT_OUT_REAL_F32 | FFT_NORM_NUMPY | FFT_REAL_EVEN)) return FFT_ERR_ARG;
   const int64_t N = dims[0], M = rank == 2 ? dims[1] : 1;
+  if ((flags & FFT_REAL_EVEN) && (rank != 2 || !(flags & FFT_IN_REAL_F32))) return FFT_ERR_ARG;
   if (rank == 1 && (!is_pow2(N) || N > (int64_t(1) << 24))) return FFT_ERR_SIZE;
   if (rank == 2 && (!is_pow2(N) || !is_pow2(M) || N > (1 << kMaxLog2Row) || M > (1 << kMaxLog2Row)))
     return FFT_ERR_SIZE;
@@ -305,9 +306,13 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
     }
     while (rb > 1 && threads_per_transform((int)N) % rb) rb /= 2;
     p->rb = rb;
-    p->w = tuned_cols_width(p.get());
-    p->chunk = filter_chunk(N, M, batch);
-    p->ws_bytes = (size_t)batch * (size_t)N * (size_t)M * sizeof(float2);
+    p->half = (flags & FFT_REAL_EVEN) != 0;
+    if (p->half && (N < 32 || M < 4 || rb < 2)) return FFT_ERR_UNSUPPORTED;
+    // columns the workspace carries: M, or 0 .. M/2 - 1 of a half spectrum
+    const int64_t mc = p->half ? M / 2 : M;
+    p->w = tuned_cols_width(p.get(), (int)mc);
+    p->chunk = filter_chunk(N, mc, batch);
+    p->ws_bytes = (size_t)batch * (size_t)N * (size_t)mc * sizeof(float2);
     p->spec_bytes = p->ws_bytes;
     // the mask gradient's per-group partial sums follow the blocked data
     p->grad_groups = grad_groups(M / p->w, batch);
@@ -352,6 +357,7 @@ int fft_plan_padded(fft_plan_t* out, const int64_t* dims0, int64_t batch, uint32
 int fft2d_spectrum(fft_plan_t p, const void* in, float* magnitude, void* workspace, void* stream) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
+  if (p->half) return FFT_ERR_UNSUPPORTED;
   if (p->batch == 0) return FFT_OK;
   if (!in || !magnitude) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
@@ -398,7 +404,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
       direction != FFT_ADJ_INVERSE)
     return FFT_ERR_ARG;
   if (p->kind != 1 && p->kind != 2) return FFT_ERR_STATE;
-  if (p->padded) return FFT_ERR_UNSUPPORTED;
+  if (p->padded || p->half) return FFT_ERR_UNSUPPORTED;
   if (p->batch == 0) return FFT_OK;
   if (!in || !out || in == out) return FFT_ERR_ARG;
   if (p->ws_bytes && !workspace) return FFT_ERR_WORKSPACE;
@@ -458,6 +464,14 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   MaskArgs mk;
   int rc = fill_mask(mask, p, &mk);
   if (rc != FFT_OK) return rc;
+  if (p->half) {
+    // the half-spectrum path needs H(-u, -v) = H(u, v)
+    const bool even_disc = mk.kind == FFT_MASK_DISC && (mk.c1 == 0.0 || mk.c1 == 0.5 * (double)p->n) &&
+                           (mk.c2 == 0.0 || mk.c2 == 0.5 * (double)p->m);
+    if (spectrum || (mk.kind != FFT_MASK_NONE && mk.kind != FFT_MASK_GAUSSIAN && mk.kind != FFT_MASK_BUTTERWORTH &&
+                     !even_disc))
+      return FFT_ERR_UNSUPPORTED;
+  }
   if (p->batch == 0) return FFT_OK;
   if (((stages & 1) && !in) || ((stages & 4) && !out)) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
@@ -486,6 +500,7 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   // stay in the memory-side cache between the passes.  A single stage covers
   // the whole batch.
   const int64_t plane = p->n * p->m;
+  const int64_t mc = p->half ? p->m / 2 : p->m;  // workspace columns
   const int64_t chunk = stages == 7 ? p->chunk : p->batch;
   for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, p->batch - b0);
@@ -495,15 +510,18 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
     float2* cspec = spectrum ? static_cast<float2*>(spectrum) + b0 * plane : nullptr;
     hipError_t e = hipSuccess;
     if (stages & 1) {
-      e = launch_rows_to_blk(p->log_m, false, pair, cin, in_f32, ws, blocks, p->rb, fwd_scale_2d(p), lr);
+      e = p->half ? launch_rows_to_blk_half(p->log_m, static_cast<const float*>(static_cast<const void*>(cin)), ws,
+                                            blocks, p->rb, fwd_scale_2d(p), lr)
+                  : launch_rows_to_blk(p->log_m, false, pair, cin, in_f32, ws, blocks, p->rb, fwd_scale_2d(p), lr);
       if (e != hipSuccess) return hip_fail(e);
     }
     if (stages & 2) {
-      e = launch_cols_filter(p->log_n, ws, cspec, nb, (int)p->m, p->rb, p->w, mk, lcn);
+      e = launch_cols_filter(p->log_n, ws, cspec, nb, (int)mc, p->rb, p->w, p->half, mk, lcn);
       if (e != hipSuccess) return hip_fail(e);
     }
     if (stages & 4) {
-      e = launch_rows_from_blk(p->log_m, true, ws, cout, out_f32, blocks, p->rb, inv_scale_2d(p), lr);
+      e = p->half ? launch_rows_c2r(p->log_m, ws, cout, out_f32, blocks, p->rb, inv_scale_2d(p), lr)
+                  : launch_rows_from_blk(p->log_m, true, ws, cout, out_f32, blocks, p->rb, inv_scale_2d(p), lr);
       if (e != hipSuccess) return hip_fail(e);
     }
   }
@@ -538,7 +556,7 @@ static int grad_impl(fftmi_plan* p, const void* in, const void* spectrum, const 
                      float* grad_mask, void* workspace, void* stream) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
-  if (p->padded) return FFT_ERR_UNSUPPORTED;
+  if (p->padded || p->half) return FFT_ERR_UNSUPPORTED;
   if (!grad_mask) return FFT_ERR_ARG;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   if (p->batch == 0) {

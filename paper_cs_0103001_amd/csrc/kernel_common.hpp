@@ -148,10 +148,12 @@ __device__ __forceinline__ float row_freq(float fj, int q) {
 template <int L, int MK>
 struct MaskEval;
 
+// value(j, q, mk) is H at row j + q*TPT of the evaluator's column.
 template <int L>
 struct MaskEval<L, FFT_MASK_NONE> {
   __device__ __forceinline__ MaskEval(const MaskArgs&, int, int, int) {}
   __device__ __forceinline__ void apply(float2 (&)[elems_per_thread(L)], int, const MaskArgs&) const {}
+  __device__ __forceinline__ float value(int, int, const MaskArgs&) const { return 1.0f; }
 };
 
 template <int L>
@@ -170,6 +172,12 @@ struct MaskEval<L, FFT_MASK_BUTTERWORTH> {
       const float p = (mk.order == 4) ? (qq * qq) * (qq * qq) : powi_pos(qq, mk.order);
       a[q] = cscale(a[q], __builtin_amdgcn_rcpf(1.0f + p));
     }
+  }
+  __device__ __forceinline__ float value(int, int q, const MaskArgs& mk) const {
+    const float fu = row_freq<L>(fj, q);
+    const float qq = fmaf(fu, fu, fv2) * mk.inv_fc2;
+    const float p = (mk.order == 4) ? (qq * qq) * (qq * qq) : powi_pos(qq, mk.order);
+    return __builtin_amdgcn_rcpf(1.0f + p);
   }
 };
 
@@ -190,6 +198,10 @@ struct MaskEval<L, FFT_MASK_GAUSSIAN> {
       a[q] = cscale(a[q], __builtin_amdgcn_exp2f(fmaf(fu, fu, fv2) * c));
     }
   }
+  __device__ __forceinline__ float value(int, int q, const MaskArgs& mk) const {
+    const float fu = row_freq<L>(fj, q);
+    return __builtin_amdgcn_exp2f(fmaf(fu, fu, fv2) * (mk.gauss_coef * 1.44269504088896340736f));
+  }
 };
 
 template <int L>
@@ -206,6 +218,11 @@ struct MaskEval<L, FFT_MASK_DISC> {
       const double du = (double)(j + q * TPT) - mk.c1;
       if (fma(du, du, dv2) <= mk.disc_b2) a[q] = make_float2(0.f, 0.f);
     }
+  }
+  __device__ __forceinline__ float value(int j, int q, const MaskArgs& mk) const {
+    constexpr int TPT = L / elems_per_thread(L);
+    const double du = (double)(j + q * TPT) - mk.c1;
+    return fma(du, du, dv2) <= mk.disc_b2 ? 0.0f : 1.0f;
   }
 };
 

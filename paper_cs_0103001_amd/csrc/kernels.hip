@@ -96,11 +96,16 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
 // Hermitian symmetry of a real sequence's DFT:
 // A = (Z[k] + conj Z[-k]) / 2, B = (Z[k] - conj Z[-k]) / 2i.
 // A tile is npt pairs (a power of two) of one block of rb rows.
-template <int L, bool INV>
+//
+// HALF: only columns 0 .. L/2-1 are stored (blocks of L/2 columns), the
+// half spectrum that a real row determines.  Column 0 carries the two real
+// values A[0] and A[L/2] of a row as one complex number (A[0] + i A[L/2]).
+template <int L, bool INV, bool HALF>
 __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* __restrict__ in,
                                                                    float2* __restrict__ ws, int rb, int npt,
                                                                    int ntiles, float scale,
                                                                    const float2* __restrict__ tws) {
+  static_assert(!HALF || !kSplitExchange, "half spectrum with whole complex LDS entries");
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT, RBY = lds_region_bytes(L, 1);
   char* reg = regions<L>();
@@ -136,7 +141,8 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
     if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
     // float4 base of this tile: block start plus the tile's first pair
-    float4* dst = reinterpret_cast<float4*>(ws + (int64_t)(t >> lsub) * L * rb) + (t & ((1 << lsub) - 1)) * npt;
+    constexpr int LC = HALF ? L / 2 : L;  // stored columns
+    float4* dst = reinterpret_cast<float4*>(ws + (int64_t)(t >> lsub) * LC * rb) + (t & ((1 << lsub) - 1)) * npt;
     const unsigned lo = fresh(lane_out);
     if constexpr (kSplitExchange) {
       float ax[E], by[E];
@@ -166,16 +172,102 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
       scatter_natural<L, kBoth>(a, j, x);
       lds_barrier();
 #pragma unroll
-      for (int i = 0; i < E; ++i) {
+      for (int i = 0; i < (HALF ? E / 2 : E); ++i) {
         const int v = v0 + i * TPT, vm = (L - v) & (L - 1);
         const float2 z = reinterpret_cast<const float2*>(xs)[lds_pad(v)];
         const float2 zm = reinterpret_cast<const float2*>(xs)[lds_pad(vm)];
-        dst[lo + i * TPT * np] =
-            make_float4(h * (z.x + zm.x), h * (z.y - zm.y), h * (z.y + zm.y), h * (zm.x - z.x));
+        float4 o = make_float4(h * (z.x + zm.x), h * (z.y - zm.y), h * (z.y + zm.y), h * (zm.x - z.x));
+        if (HALF && i == 0 && v0 == 0) {
+          // A[0], B[0] are 2h Re Z[0], 2h Im Z[0]; A[L/2], B[L/2] likewise from Z[L/2]
+          const float2 zh = reinterpret_cast<const float2*>(xs)[lds_pad(L / 2)];
+          o = make_float4(2.f * h * z.x, 2.f * h * zh.x, 2.f * h * z.y, 2.f * h * zh.y);
+        }
+        dst[lo + i * TPT * np] = o;
       }
     }
 #pragma unroll
     for (int q = 0; q < E; ++q) a[q] = nx[q];
+  }
+}
+
+// Inverse row transforms of a half spectrum (last pass of the half-spectrum
+// path).  Two rows' half spectra Y1, Y2 (columns 0 .. L/2-1 of the blocked
+// layout, column 0 holding Y(0) + i Y(L/2)) give W = Y1 + i Y2 on all L
+// columns through Y(L - v) = conj Y(v); the inverse transform of W is
+// y1 + i y2 with both rows real.  A tile is npt pairs of one block, loaded as
+// float4 (Y1(v), Y2(v)) and staged through LDS.
+template <int L, bool F32>
+__global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __restrict__ ws, void* __restrict__ out,
+                                                                int rb, int npt, int ntiles, float scale,
+                                                                const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT, RBY = lds_region_bytes(L, 1), H = L / 2, EH = E / 2;
+  static_assert(L >= 2 && !kSplitExchange, "half spectrum rows");
+  char* reg = regions<L>();
+  const int np = rb >> 1;
+  const int lsub = ilog2_pow2(np / npt);
+  const int tid = threadIdx.x, p = tid / TPT, j = tid - p * TPT;
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  float2* x = reinterpret_cast<float2*>(reg + p * RBY);
+  const unsigned lane = (unsigned)(j * np);
+  float4 a[EH], nx[EH];
+  auto pair_of = [&](int t) __attribute__((always_inline)) { return (t & ((1 << lsub) - 1)) * npt + p; };
+  auto load = [&](float4(&d)[EH], int t) __attribute__((always_inline)) {
+    const float4* b = reinterpret_cast<const float4*>(ws + (int64_t)(t >> lsub) * H * rb) + pair_of(t);
+    const unsigned l = fresh(lane);
+#pragma unroll
+    for (int q = 0; q < EH; ++q) d[q] = ld(b, l + q * TPT * np);
+  };
+  int n = blockIdx.x;
+  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+#pragma unroll
+  for (int q = 0; q < EH; ++q) asm volatile("" : "+v"(a[q].x), "+v"(a[q].y), "+v"(a[q].z), "+v"(a[q].w));
+  for (; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    lds_barrier();  // the previous tile's readers of x are done
+#pragma unroll
+    for (int q = 0; q < EH; ++q) {
+      const int v = j + q * TPT;
+      x[lds_pad(v)] = make_float2(a[q].x, a[q].y);
+      x[lds_pad(H + v)] = make_float2(a[q].z, a[q].w);
+    }
+    lds_barrier();
+    float2 w[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+      const int u = j + q * TPT;
+      if (q < EH) {
+        const float2 y1 = x[lds_pad(u)], y2 = x[lds_pad(H + u)];
+        w[q] = (u == 0) ? make_float2(y1.x, y2.x) : make_float2(y1.x - y2.y, y1.y + y2.x);
+      } else {
+        const int k = (u == H) ? 0 : L - u;  // u = H reads the packed column 0
+        const float2 y1 = x[lds_pad(k)], y2 = x[lds_pad(H + k)];
+        w[q] = (u == H) ? make_float2(y1.y, y2.y) : make_float2(y1.x + y2.y, y2.x - y1.y);
+      }
+    }
+    fft_reg<L, true, S::TWM>(w, j, reinterpret_cast<char*>(x), tw);
+    const int64_t r0 = (int64_t)(t >> lsub) * rb + 2 * pair_of(t);
+    if constexpr (F32) {
+      float* o = static_cast<float*>(out) + r0 * L;
+      const unsigned l = fresh((unsigned)j);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        o[l + q * TPT] = w[q].x * scale;
+        o[l + L + q * TPT] = w[q].y * scale;
+      }
+    } else {
+      float2* o = static_cast<float2*>(out) + r0 * L;
+      const unsigned l = fresh((unsigned)j);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        o[l + q * TPT] = make_float2(w[q].x * scale, 0.f);
+        o[l + L + q * TPT] = make_float2(w[q].y * scale, 0.f);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < EH; ++q) a[q] = nx[q];
   }
 }
 
@@ -293,10 +385,19 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
 // is w columns of one image (ltiles = log2(M / w) tiles per image); the tile
 // base is image * L * M + v0 * rb and the lane offset jh*M*rb + c*rb + s.
 // Tensor-mask values are read after the forward transform.
-template <int L, int MK>
+//
+// HALF: the workspace holds the half spectrum of real images (M = half of the
+// image's columns; frequencies are those of 2M columns).  Column 0 holds the
+// sequences c0 = X(., 0) and cn = X(., M) of the full spectrum as c0 + i cn;
+// both are transforms of real columns, so after the column transform
+// C0(u) = (Z(u) + conj Z(-u)) / 2 and Cn(u) = (Z(u) - conj Z(-u)) / 2i, each
+// is multiplied by its own mask column, and Z' = H0 C0 + i Hn Cn is
+// transformed back.
+template <int L, int MK, bool HALF>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict__ ws, float2* __restrict__ save, int M,
                                                       int rb, int w, int ltiles, int ntiles, MaskArgs mk,
                                                       const float2* __restrict__ tws) {
+  static_assert(!HALF || (!kSplitExchange && MK != FFT_MASK_TENSOR_F32), "half spectrum: analytic masks");
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
@@ -330,8 +431,37 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
         for (int q = 0; q < E; ++q) sb[f_lane + q * qs] = a[q];
       }
     }
-    const MaskEval<L, MK> me(mk, ln.j, v, M);
-    me.apply(a, ln.j, mk);
+    const int mfreq = HALF ? 2 * M : M;  // columns of the frequency grid
+    if constexpr (HALF) {
+      if ((t & tmask) == 0) {
+      // the tile with column 0: every thread passes its values through LDS
+      // (barriers are workgroup-wide); column 0's threads split c0 and cn
+      lds_barrier();
+      scatter_natural<L, kBoth>(a, ln.j, x);
+      lds_barrier();
+      const MaskEval<L, MK> m0(mk, ln.j, 0, mfreq), mn(mk, ln.j, M, mfreq), mv(mk, ln.j, v, mfreq);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int u = ln.j + q * TPT;
+        if (ln.c == 0) {
+          const float2 z = a[q];
+          const float2 zm = reinterpret_cast<const float2*>(x)[lds_pad((L - u) & (L - 1))];
+          const float h0 = m0.value(ln.j, q, mk), hn = mn.value(ln.j, q, mk);
+          const float c0x = 0.5f * (z.x + zm.x), c0y = 0.5f * (z.y - zm.y);
+          const float cnx = 0.5f * (z.y + zm.y), cny = 0.5f * (zm.x - z.x);
+          a[q] = make_float2(h0 * c0x - hn * cny, h0 * c0y + hn * cnx);
+        } else {
+          a[q] = cscale(a[q], mv.value(ln.j, q, mk));
+        }
+      }
+      } else {
+        const MaskEval<L, MK> me(mk, ln.j, v, mfreq);
+        me.apply(a, ln.j, mk);
+      }
+    } else {
+      const MaskEval<L, MK> me(mk, ln.j, v, mfreq);
+      me.apply(a, ln.j, mk);
+    }
     fft_reg<L, true, S::TWM>(a, ln.j, x, tw);
     {
       const unsigned f_lane = fresh(lane);
@@ -781,8 +911,8 @@ int rows_per_tile(int rb, int target) {
 
 template <int LG>
 struct RowsToBlk {
-  static hipError_t run(bool inv, bool pair, const void* in, bool in_f32, float2* ws, int64_t blocks, int rb,
-                        float scale, const Launch& lc) {
+  static hipError_t run(bool inv, bool pair, bool half, const void* in, bool in_f32, float2* ws, int64_t blocks,
+                        int rb, float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const float2* tw = twiddle_src<L>(lc);
     if (pair && rb >= 2) {
@@ -792,13 +922,16 @@ struct RowsToBlk {
         const int lds = tw_bytes<L>() + npt * lds_region_bytes(L, 1);
         const float* fin = static_cast<const float*>(in);
         const int64_t ntiles = blocks * (rb / 2 / npt);
-        if (inv)
-          return go(k_rows_to_blk_pair<L, true>, ntiles, npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles,
-                    scale, tw);
-        return go(k_rows_to_blk_pair<L, false>, ntiles, npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles,
-                  scale, tw);
+        if constexpr (L >= 2) {
+          if (half)
+            return go(inv ? k_rows_to_blk_pair<L, true, true> : k_rows_to_blk_pair<L, false, true>, ntiles,
+                      npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw);
+        }
+        return go(inv ? k_rows_to_blk_pair<L, true, false> : k_rows_to_blk_pair<L, false, false>, ntiles, npt * TPT,
+                  lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw);
       }
     }
+    if (half) return hipErrorInvalidValue;
     const int nt = rows_per_tile<L>(rb, 512);
     const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
     const int64_t ntiles = blocks * (rb / nt);
@@ -826,9 +959,29 @@ struct RowsFromBlk {
 };
 
 template <int LG>
-struct ColsFilter {
-  static hipError_t run(float2* ws, float2* save, int64_t nimg, int M, int rb, int w, const MaskArgs& mk,
+struct RowsC2R {
+  static hipError_t run(const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
                         const Launch& lc) {
+    constexpr int L = 1 << LG, TPT = threads_per_transform(L);
+    if constexpr (L < 2) {
+      return hipErrorInvalidValue;
+    } else {
+      if (rb < 2) return hipErrorInvalidValue;
+      const int npt = pair_per_tile<L>(rb);
+      const int lds = tw_bytes<L>() + npt * lds_region_bytes(L, 1);
+      if (lds > kLdsBytes || npt * TPT > max_block<L>()) return hipErrorInvalidValue;
+      const int64_t ntiles = blocks * (rb / 2 / npt);
+      return go(out_f32 ? k_rows_c2r_pair<L, true> : k_rows_c2r_pair<L, false>, ntiles, npt * TPT, lds, lc.stream, ws,
+                out, rb, npt, (int)ntiles, scale, twiddle_src<L>(lc));
+    }
+  }
+};
+
+template <int LG>
+struct ColsFilter {
+  template <bool HALF>
+  static hipError_t launch(float2* ws, float2* save, int64_t nimg, int M, int rb, int w, const MaskArgs& mk,
+                           const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = M / w;
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
@@ -837,21 +990,26 @@ struct ColsFilter {
     const int lt = ilog2c(tiles);
     switch (mk.kind) {
       case FFT_MASK_TENSOR_F32:
-        return go(k_cols_filter<L, FFT_MASK_TENSOR_F32>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        if constexpr (HALF) return hipErrorInvalidValue;
+        return go(k_cols_filter<L, FFT_MASK_TENSOR_F32, false>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
                   (int)ntiles, mk, tw);
       case FFT_MASK_GAUSSIAN:
-        return go(k_cols_filter<L, FFT_MASK_GAUSSIAN>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        return go(k_cols_filter<L, FFT_MASK_GAUSSIAN, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
                   (int)ntiles, mk, tw);
       case FFT_MASK_BUTTERWORTH:
-        return go(k_cols_filter<L, FFT_MASK_BUTTERWORTH>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
-                  (int)ntiles, mk, tw);
+        return go(k_cols_filter<L, FFT_MASK_BUTTERWORTH, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w,
+                  lt, (int)ntiles, mk, tw);
       case FFT_MASK_DISC:
-        return go(k_cols_filter<L, FFT_MASK_DISC>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        return go(k_cols_filter<L, FFT_MASK_DISC, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
                   (int)ntiles, mk, tw);
       default:
-        return go(k_cols_filter<L, FFT_MASK_NONE>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        return go(k_cols_filter<L, FFT_MASK_NONE, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
                   (int)ntiles, mk, tw);
     }
+  }
+  static hipError_t run(float2* ws, float2* save, int64_t nimg, int M, int rb, int w, bool half, const MaskArgs& mk,
+                        const Launch& lc) {
+    return half ? launch<true>(ws, save, nimg, M, rb, w, mk, lc) : launch<false>(ws, save, nimg, M, rb, w, mk, lc);
   }
 };
 
@@ -919,13 +1077,16 @@ struct ColsStrided {
     return RowsRm<K>::run(inv, in, in_f32, out, out_f32, rows, scale, lc);
 #define FFTMI_CASE_RowsToBlk(K) \
   case K:                       \
-    return RowsToBlk<K>::run(inv, pair, in, in_f32, ws, blocks, rb, scale, lc);
+    return RowsToBlk<K>::run(inv, pair, half, in, in_f32, ws, blocks, rb, scale, lc);
+#define FFTMI_CASE_RowsC2R(K) \
+  case K:                     \
+    return RowsC2R<K>::run(ws, out, out_f32, blocks, rb, scale, lc);
 #define FFTMI_CASE_RowsFromBlk(K) \
   case K:                         \
     return RowsFromBlk<K>::run(inv, ws, out, out_f32, blocks, rb, scale, lc);
 #define FFTMI_CASE_ColsFilter(K) \
   case K:                        \
-    return ColsFilter<K>::run(ws, save, nimg, M, rb, w, mask, lc);
+    return ColsFilter<K>::run(ws, save, nimg, M, rb, w, half, mask, lc);
 #define FFTMI_CASE_ColsFft(K) \
   case K:                     \
     return ColsFft<K>::run(inv, ws, nimg, M, rb, w, lc);
@@ -943,7 +1104,19 @@ hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void
 
 hipError_t launch_rows_to_blk(int log2L, bool inv, bool pair, const void* in, bool in_f32, float2* ws,
                               int64_t blocks, int rb, float scale, const Launch& lc) {
+  const bool half = false;
   FFTMI_DISPATCH(RowsToBlk, log2L)
+}
+
+hipError_t launch_rows_to_blk_half(int log2L, const float* in, float2* ws, int64_t blocks, int rb, float scale,
+                                   const Launch& lc) {
+  const bool inv = false, pair = true, half = true, in_f32 = true;
+  FFTMI_DISPATCH(RowsToBlk, log2L)
+}
+
+hipError_t launch_rows_c2r(int log2L, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
+                           const Launch& lc) {
+  FFTMI_DISPATCH(RowsC2R, log2L)
 }
 
 hipError_t launch_rows_from_blk(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks,
@@ -951,7 +1124,7 @@ hipError_t launch_rows_from_blk(int log2L, bool inv, const float2* ws, void* out
   FFTMI_DISPATCH(RowsFromBlk, log2L)
 }
 
-hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w,
+hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w, bool half,
                               const MaskArgs& mask, const Launch& lc) {
   FFTMI_DISPATCH(ColsFilter, log2L)
 }

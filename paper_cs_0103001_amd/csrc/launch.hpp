@@ -41,14 +41,27 @@ hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void
 hipError_t launch_rows_to_blk(int log2L, bool inv, bool pair, const void* in, bool in_f32, float2* ws,
                               int64_t blocks, int rb, float scale, const Launch& lc);
 
+// Half-spectrum path for real rows (pass one): rows in pairs, columns
+// 0 .. L/2-1 of each row's spectrum into blocks of L/2 columns, column 0
+// holding A[0] + i A[L/2].  rb even.
+hipError_t launch_rows_to_blk_half(int log2L, const float* in, float2* ws, int64_t blocks, int rb, float scale,
+                                   const Launch& lc);
+
+// Half-spectrum path, last pass: inverse row transforms of the blocked half
+// spectra (two rows per complex transform) into real rows (float32, or
+// complex64 with zero imaginary parts).  rb even.
+hipError_t launch_rows_c2r(int log2L, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
+                           const Launch& lc);
+
 // Row pass out of the blocked layout into row-major output.
 hipError_t launch_rows_from_blk(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks,
                                 int rb, float scale, const Launch& lc);
 
 // Column pass on the blocked layout (column length L = N): forward transform,
 // mask multiply, inverse transform, in place.  save != nullptr also stores the
-// forward spectrum (blocked layout).
-hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w,
+// forward spectrum (blocked layout).  half: the workspace holds M columns of a
+// half spectrum (see launch_rows_to_blk_half; analytic masks only).
+hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w, bool half,
                               const MaskArgs& mask, const Launch& lc);
 
 // Column pass on the blocked layout: one unscaled transform, in place.

@@ -42,6 +42,8 @@ struct fftmi_plan {
   // padded to n x m, the next powers of two), and the workspace offsets of
   // the padded input and the padded (uncropped) output
   bool padded = false;
+  // rank 2 with FFT_REAL_EVEN: the workspace holds half spectra
+  bool half = false;
   int64_t n0 = 0, m0 = 0;
   size_t pad_in_off = 0, pad_out_off = 0;
   // rank 1 beyond one LDS pass: four-step split N = N1 * N2
@@ -66,7 +68,7 @@ void plan_unregister(fftmi_plan* p);
 int widest_cols_tile(int log2L, int cols, int wmax);
 
 // Column tile width for a rank-2 plan (autotuned value if one is cached).
-int tuned_cols_width(const fftmi_plan* p);
+int tuned_cols_width(const fftmi_plan* p, int cols);
 
 // Images per chunk of the whole filter: the chunk's complex64 intermediate
 // stays within half of the memory-side cache (256 MiB on MI355X), so the

@@ -23,7 +23,7 @@ int widest_cols_tile(int log2L, int cols, int wmax) {
   return w;
 }
 
-int tuned_cols_width(const fftmi_plan* p) {
+int tuned_cols_width(const fftmi_plan* p, int cols) {
   // one 256-thread transform per workgroup for long columns, more for short
   const int tpt = threads_per_transform(1 << p->log_n);
   int w = std::max(1, 256 / tpt);
@@ -31,7 +31,7 @@ int tuned_cols_width(const fftmi_plan* p) {
     const int v = std::atoi(env);
     if (v >= 1 && (v & (v - 1)) == 0) w = v;
   }
-  return widest_cols_tile(p->log_n, (int)p->m, w);
+  return widest_cols_tile(p->log_n, cols, w);
 }
 
 int64_t filter_chunk(int64_t N, int64_t M, int64_t batch) {
