@@ -126,14 +126,15 @@ def _ragged_one(args):
 def ragged_batch(sizes, workers: int = 1) -> np.ndarray:
     """Images 0..len(sizes)-1 of the ragged batch packed back to back (float32,
     image i row-major at offset sum_{j<i} sizes[j]^2).  workers > 1 generates
-    them in a spawned process pool (same values)."""
+    them on a thread pool (numpy releases the interpreter lock in the heavy
+    steps; no child processes; same values)."""
     total = sum(int(s) * int(s) for s in sizes)
     out = np.empty(total, dtype=np.float32)
     jobs = list(enumerate(int(s) for s in sizes))
     if workers > 1 and len(jobs) > 1:
-        import multiprocessing as mp
-        with mp.get_context("spawn").Pool(workers) as pool:
-            imgs = pool.map(_ragged_one, jobs, chunksize=4)
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            imgs = list(ex.map(_ragged_one, jobs))
     else:
         imgs = [_ragged_one(j) for j in jobs]
     off = 0
