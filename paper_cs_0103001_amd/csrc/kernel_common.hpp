@@ -93,6 +93,26 @@ __device__ __forceinline__ T ld(const T* __restrict__ base, unsigned off) {
   return __ldg(base + off);
 }
 
+// Streaming accesses: data read or written exactly once by the whole path
+// (the input image, the final output) carry the non-temporal hint, so they
+// displace less of the intermediate that the next pass reads from the caches
+// (the memory-side cache holds a 4096^2 complex64 image between passes).
+typedef float fftmi_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float ld_nt(const float* __restrict__ base, unsigned off) {
+  return __builtin_nontemporal_load(base + off);
+}
+__device__ __forceinline__ float2 ld_nt(const float2* __restrict__ base, unsigned off) {
+  const fftmi_f2v v = __builtin_nontemporal_load(reinterpret_cast<const fftmi_f2v*>(base + off));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(float2* p, float2 v) {
+  fftmi_f2v w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<fftmi_f2v*>(p));
+}
+
 // A lane offset made opaque where it is used: the per-element offsets
 // lane + q*stride are then computed next to the access instead of being
 // hoisted out of the tile loop and held in registers for its whole length.

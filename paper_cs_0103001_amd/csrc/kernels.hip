@@ -131,7 +131,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
     const float* b = in + first_row(t) * L;
     const unsigned l = fresh(lane_in);
 #pragma unroll
-    for (int q = 0; q < E; ++q) d[q] = make_float2(ld(b, l + q * TPT), ld(b, l + L + q * TPT));
+    for (int q = 0; q < E; ++q) d[q] = make_float2(ld_nt(b, l + q * TPT), ld_nt(b, l + L + q * TPT));
   };
   int n = blockIdx.x;
   if (n < ntiles) load(a, (int)tile_of(n, ntiles));
@@ -254,16 +254,16 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __
       const unsigned l = fresh((unsigned)j);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        o[l + q * TPT] = w[q].x * scale;
-        o[l + L + q * TPT] = w[q].y * scale;
+        st_nt(&o[l + q * TPT], w[q].x * scale);
+        st_nt(&o[l + L + q * TPT], w[q].y * scale);
       }
     } else {
       float2* o = static_cast<float2*>(out) + r0 * L;
       const unsigned l = fresh((unsigned)j);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        o[l + q * TPT] = make_float2(w[q].x * scale, 0.f);
-        o[l + L + q * TPT] = make_float2(w[q].y * scale, 0.f);
+        st_nt(&o[l + q * TPT], make_float2(w[q].x * scale, 0.f));
+        st_nt(&o[l + L + q * TPT], make_float2(w[q].y * scale, 0.f));
       }
     }
 #pragma unroll
@@ -298,14 +298,14 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk(const void* __rest
       {
         const unsigned f_lane_in = fresh(lane_in);
 #pragma unroll
-        for (int q = 0; q < E; ++q) d[q] = make_float2(ld(b, f_lane_in + q * TPT), 0.f);
+        for (int q = 0; q < E; ++q) d[q] = make_float2(ld_nt(b, f_lane_in + q * TPT), 0.f);
       }
     } else {
       const float2* b = static_cast<const float2*>(in) + row0(t) * L;
       {
         const unsigned f_lane_in = fresh(lane_in);
 #pragma unroll
-        for (int q = 0; q < E; ++q) d[q] = ld(b, f_lane_in + q * TPT);
+        for (int q = 0; q < E; ++q) d[q] = ld_nt(b, f_lane_in + q * TPT);
       }
     }
   };
@@ -364,14 +364,14 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
       {
         const unsigned f_lane_out = fresh(lane_out);
 #pragma unroll
-        for (int q = 0; q < E; ++q) b[f_lane_out + q * TPT] = a[q].x * scale;
+        for (int q = 0; q < E; ++q) st_nt(&b[f_lane_out + q * TPT], a[q].x * scale);
       }
     } else {
       float2* b = static_cast<float2*>(out) + r0 * L;
       {
         const unsigned f_lane_out = fresh(lane_out);
 #pragma unroll
-        for (int q = 0; q < E; ++q) b[f_lane_out + q * TPT] = cscale(a[q], scale);
+        for (int q = 0; q < E; ++q) st_nt(&b[f_lane_out + q * TPT], cscale(a[q], scale));
       }
     }
 #pragma unroll
