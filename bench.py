@@ -263,9 +263,10 @@ def main():
         Kl = max(5, K // 5)
         ms_fb = timed(torch, fwd_bwd, Kl, 2)
         pxl = Bl * Nl * Ml
-        # FFT kernels: forward 44 + saved spectrum 8 + tensor mask 4; backward:
-        # rows of x - c (read 4, write 8), columns (read 8 + spectrum 8)
-        fb_bytes = (56 + 28) * pxl
+        # library kernels: forward rows 4+8, columns 8+8 + saved spectrum 8 +
+        # tensor mask 4, last rows 8 + x 4 + c 4 (no image written); backward
+        # rows of x - c (4 + 4 read, 8 written), columns (8 + spectrum 8)
+        fb_bytes = (56 + 32) * pxl
         planl = api.get_plan(2, (Nl, Ml), Bl, B.FFT_IN_REAL_F32, dev)
         wsl = planl.workspace()
         ol = torch.empty((Bl, Nl, Ml), dtype=torch.complex64, device=dev)
@@ -277,9 +278,8 @@ def main():
         result["fwd_bwd"] = {"workload": "learn_1024: batch 64 of 1024x1024, learnable float32 mask at 1, "
                                          "MSE loss (fused filter+MSE op), mask gradient",
                              "ms_per_step": round(ms_fb, 4), "GB/s": round(fb_gbs, 1),
-                             "byte_model": "84 B/px of FFT kernels (fwd 44 + saved spectrum 8 + mask 4; "
-                                           "bwd 12 rows + 16 columns); the step also runs torch's elementwise "
-                                           "loss terms",
+                             "byte_model": "88 B/px of library kernels (fwd 12 rows + 28 columns with saved "
+                                           "spectrum and mask + 16 loss rows; bwd 16 rows of x - c + 16 columns)",
                              "plain_same_batch_ms": round(ms_pl, 4), "plain_same_batch_GB/s": round(plain_gbs, 1),
                              "time_vs_plain_same_batch": round(ms_fb / ms_pl, 3),
                              "ns_per_px": round(ms_fb * 1e6 / pxl, 4),

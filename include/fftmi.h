@@ -178,23 +178,41 @@ int fft_spectrum_size(fft_plan_t plan, size_t* bytes);
 int fft2d_filter_mask_grad(fft_plan_t plan, const void* grad_y, const void* spectrum, float* grad_mask,
                            void* workspace, void* stream);
 
-/* Mask gradient of the filtered mean-squared error, in the form that stays
- * accurate where y is close to the target.  For y_b = 2D-IDFT(m . X_b),
- * X_b = 2D-DFT(x_b) and a loss L = (weight/2) sum_b sum |y_b - c_b|^2:
+/* Fused forward of the filtered mean-squared error for real images (a plan
+ * with FFT_IN_REAL_F32, without padding or FFT_REAL_EVEN):
+ *   loss[0] = weight * sum_b sum_{u,v} |y_b[u][v] - c_b[u][v]|^2,
+ *   y_b = 2D-IDFT(m . X_b), X_b = 2D-DFT(x_b) (eq. 5 and the 2D-IDFT),
+ * evaluated as y - c = 2D-IDFT((m - 1) . X) + (x - c), which holds exactly
+ * because the transform pair inverts, so no difference of nearly equal
+ * float32 values is formed where m is close to 1.  y is not written; X is
+ * stored to `spectrum` (fft2d_filter_save's layout) for the gradient below.
+ *   x, c    float32 [B][N][M] (device)
+ *   mask    m, float32 [N][M] (device)
+ *   weight  e.g. 1 / (B N M) for the mean over all pixels
+ *   loss    one float32 on the device
+ * The sum is taken in float32 within each tile of rows and in float64 across
+ * tiles, in a fixed order.  Errors: FFT_ERR_ARG, FFT_ERR_STATE (not rank 2,
+ * other device), FFT_ERR_UNSUPPORTED (other input type, padded or
+ * FFT_REAL_EVEN plans, N < 2), FFT_ERR_WORKSPACE, FFT_ERR_HIP. */
+int fft2d_filter_mse(fft_plan_t plan, const float* x, const float* c, const float* mask, float weight, void* spectrum,
+                     float* loss, void* workspace, void* stream);
+
+/* Mask gradient of (weight/2) sum_b sum |y_b - c_b|^2 for the same y:
  *   dL/dm = weight * sum_b [ Re(conj X_b . 2D-IDFT^H (x_b - c_b))
  *                            + (a_inv / a_fwd) (m - 1) |X_b|^2 ]
- * because 2D-DFT(y_b - c_b) = (m - 1) X_b + 2D-DFT(x_b - c_b) (the transform
- * pair of eq. 5 and the 2D-IDFT inverts exactly), where a_fwd and a_inv are
- * the forward and inverse scales (N/M for FFT_NORM_PAPER).  At m = 1 no
+ * because 2D-DFT(y_b - c_b) = (m - 1) X_b + 2D-DFT(x_b - c_b); a_fwd and a_inv
+ * are the forward and inverse scales (N/M for FFT_NORM_PAPER).  At m = 1 no
  * difference y - c of nearly equal values is formed.
- *   resid     x - c per image: float32 [B][N][M] for an FFT_IN_REAL_F32 plan,
- *             complex64 otherwise (device)
- *   spectrum  X saved by fft2d_filter_save with this plan (device)
+ *   x, c      the images and targets, float32 [B][N][M] for an FFT_IN_REAL_F32
+ *             plan (x - c is formed as they are loaded); c == NULL means x is
+ *             already the residual x - c (then also complex64 for complex plans)
+ *   spectrum  X saved by fft2d_filter_save or fft2d_filter_mse with this plan
  *   mask      m, float32 [N][M] row-major (device, required)
  *   weight    e.g. 2 / (B N M) for the mean over all pixels
- * Batch order and errors as fft2d_filter_mask_grad. */
-int fft2d_filter_mse_grad(fft_plan_t plan, const void* resid, const void* spectrum, const float* mask, float weight,
-                          float* grad_mask, void* workspace, void* stream);
+ * Batch order and errors as fft2d_filter_mask_grad; FFT_ERR_UNSUPPORTED when
+ * c is given for a complex plan. */
+int fft2d_filter_mse_grad(fft_plan_t plan, const void* x, const void* c, const void* spectrum, const float* mask,
+                          float weight, float* grad_mask, void* workspace, void* stream);
 
 /* Ragged batch: `count` square images of power-of-two sides sizes[i] (host
  * array, copied; 1 <= sizes[i] <= 2048), packed back to back in one buffer:

@@ -65,7 +65,8 @@ _SIGS = {
     "fft2d_filter_stage": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _MASKP, _P, _P]),
     "fft2d_filter_save": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P, _P]),
     "fft2d_filter_mask_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
-    "fft2d_filter_mse_grad": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _P, _P, _P]),
+    "fft2d_filter_mse_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P]),
+    "fft2d_filter_mse": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
     "fft_plan_ragged": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int64, _I64P, ctypes.c_uint32]),
     "fft2d_filter_ragged": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
     "fft_plan_tune": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
@@ -175,9 +176,14 @@ def fft2d_filter_mask_grad(plan, grad_y, spectrum, grad_mask, workspace, stream)
           "fft2d_filter_mask_grad")
 
 
-def fft2d_filter_mse_grad(plan, resid, spectrum, mask, weight, grad_mask, workspace, stream):
-    check(lib().fft2d_filter_mse_grad(plan, resid, spectrum, mask, float(weight), grad_mask, workspace, stream),
+def fft2d_filter_mse_grad(plan, x, c, spectrum, mask, weight, grad_mask, workspace, stream):
+    check(lib().fft2d_filter_mse_grad(plan, x, c, spectrum, mask, float(weight), grad_mask, workspace, stream),
           "fft2d_filter_mse_grad")
+
+
+def fft2d_filter_mse(plan, x, c, mask, weight, spectrum, loss, workspace, stream):
+    check(lib().fft2d_filter_mse(plan, x, c, mask, float(weight), spectrum, loss, workspace, stream),
+          "fft2d_filter_mse")
 
 
 def fft2d_filter_ragged(plan, inp, out, mask, workspace, stream):

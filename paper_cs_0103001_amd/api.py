@@ -212,21 +212,44 @@ def mask_grad(grad_y, spectrum, norm="paper"):
     return out
 
 
-def mse_grad(resid, spectrum, mask, weight, norm="paper"):
-    """weight * sum_b [Re(conj X_b . 2D-IDFT^H resid_b) + (a_inv/a_fwd)(m - 1)|X_b|^2]:
-    the mask gradient of (weight/2) sum |2D-IDFT(m . X) - c|^2 with resid = x - c."""
-    r, fin = _prep(resid)
+def mse_grad(x, c, spectrum, mask, weight, norm="paper"):
+    """weight * sum_b [Re(conj X_b . 2D-IDFT^H (x_b - c_b)) + (a_inv/a_fwd)(m - 1)|X_b|^2]:
+    the mask gradient of (weight/2) sum |2D-IDFT(m . X) - c|^2; c=None means x is
+    already the residual x - c."""
+    r, fin = _prep(x)
     N, M = r.shape[-2], r.shape[-1]
     batch = r.numel() // (N * M)
     if mask.dtype != torch.float32 or tuple(mask.shape) != (N, M):
         raise ValueError("mask must be float32 [%d, %d]" % (N, M))
     m = mask.contiguous()
+    cc = None
+    if c is not None:
+        cc, _ = _prep(c)
     plan = get_plan(2, (N, M), batch, fin | _NORM[norm], r.device)
     out = torch.empty((N, M), dtype=torch.float32, device=r.device)
     ws = plan.workspace()
-    B.fft2d_filter_mse_grad(plan.h, _ptr(r), _ptr(spectrum), _ptr(m), weight, _ptr(out), _ptr(ws),
+    B.fft2d_filter_mse_grad(plan.h, _ptr(r), _ptr(cc), _ptr(spectrum), _ptr(m), weight, _ptr(out), _ptr(ws),
                             _stream(r.device))
     return out
+
+
+def filter_mse(x, c, mask, weight, norm="paper"):
+    """(loss, spectrum): loss = weight * sum |2D-IDFT(m . 2D-DFT(x)) - c|^2 (a
+    0-dim float32 tensor) for float32 x, c [..., N, M], and the saved spectrum."""
+    x, fin = _prep(x)
+    c, _ = _prep(c)
+    if fin != B.FFT_IN_REAL_F32:
+        raise TypeError("filter_mse takes float32 images")
+    N, M = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (N * M)
+    m = mask.contiguous()
+    plan = get_plan(2, (N, M), batch, fin | _NORM[norm], x.device)
+    spec = torch.empty(max(plan.spectrum_bytes, 1), dtype=torch.uint8, device=x.device)
+    loss = torch.empty((), dtype=torch.float32, device=x.device)
+    ws = plan.workspace()
+    B.fft2d_filter_mse(plan.h, _ptr(x), _ptr(c), _ptr(m), weight, _ptr(spec), _ptr(loss), _ptr(ws),
+                       _stream(x.device))
+    return loss, spec
 
 
 def filter_ragged(packed, sizes, mask, real_output=False):

@@ -61,30 +61,28 @@ class FFTFilterMSEFn(torch.autograd.Function):
     def forward(ctx, x, clean, mask):
         if x.dtype != torch.float32 or clean.dtype != torch.float32:
             raise TypeError("fft_filter_mse takes float32 images")
-        m = mask.detach()
-        d = (x - clean).contiguous()
-        u, spec = api.fft2d_filter(x, (m - 1.0).contiguous(), spectrum=True)
-        ur = torch.view_as_real(u)
-        re = ur[..., 0] + d
-        im = ur[..., 1]
+        m = mask.detach().contiguous()
+        x = x.contiguous()
+        clean = clean.contiguous()
         K = clean.numel()
-        loss = (re.square().sum() + im.square().sum()) / K
-        ctx.save_for_backward(spec, d, re, im, m)
+        loss, spec = api.filter_mse(x, clean, m, 1.0 / K)
+        ctx.save_for_backward(spec, x, clean, m)
         ctx.K = K
         return loss
 
     @staticmethod
     def backward(ctx, gL):
-        spec, d, re, im, m = ctx.saved_tensors
+        spec, x, clean, m = ctx.saved_tensors
         K = ctx.K
         gx = gc = gm = None
         if ctx.needs_input_grad[2]:
-            gm = api.mse_grad(d, spec, m, 2.0 / K) * gL
-        if ctx.needs_input_grad[0]:
-            r = torch.complex(re, im)
-            gx = api.fft2d_filter(r, m, real_output=True) * (2.0 / K * gL)
-        if ctx.needs_input_grad[1]:
-            gc = re * (-2.0 / K * gL)
+            gm = api.mse_grad(x, clean, spec, m, 2.0 / K) * gL
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            r = api.fft2d_filter(x, m) - clean  # y - c (only for the image gradients)
+            if ctx.needs_input_grad[0]:
+                gx = api.fft2d_filter(r, m, real_output=True) * (2.0 / K * gL)
+            if ctx.needs_input_grad[1]:
+                gc = r.real * (-2.0 / K * gL)
         return gx, gc, gm
 
 

@@ -320,6 +320,11 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       p->ws_bytes = (p->ws_bytes + 255) & ~(size_t)255;
       p->ws_bytes += (size_t)p->grad_groups * (size_t)N * (size_t)M * sizeof(float);
     }
+    // then the fused MSE forward's per-tile loss sums (at most one per row)
+    if (!p->half) {
+      p->loss_off = (p->ws_bytes + 255) & ~(size_t)255;
+      p->ws_bytes = p->loss_off + (size_t)std::max<int64_t>(batch * N, 1) * sizeof(float);
+    }
   }
   plan_register(p.get());
   *out = p.release();
@@ -552,8 +557,8 @@ int fft2d_filter_save(fft_plan_t p, const void* in, void* out, const fft_mask* m
 // residual of the fused MSE form) is forward-transformed in the blocked
 // layout, then the column kernel accumulates Re(conj X_b . T(in_b)) over the
 // batch in groups of consecutive images.
-static int grad_impl(fftmi_plan* p, const void* in, const void* spectrum, const float* mask, float weight,
-                     float* grad_mask, void* workspace, void* stream) {
+static int grad_impl(fftmi_plan* p, const void* in, const void* in2, const void* spectrum, const float* mask,
+                     float weight, float* grad_mask, void* workspace, void* stream) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
   if (p->padded || p->half) return FFT_ERR_UNSUPPORTED;
@@ -575,7 +580,10 @@ static int grad_impl(fftmi_plan* p, const void* in, const void* spectrum, const 
   const int64_t blocks = p->batch * p->n / p->rb;
   Launch lr = launch_for(st, p->tables, p->log_m);
   // unscaled forward transform of the rows; the adjoint's scale goes into w_lin
-  hipError_t e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
+  if (in2 && !pair) return FFT_ERR_UNSUPPORTED;
+  hipError_t e = in2 ? launch_rows_to_blk_diff(p->log_m, static_cast<const float*>(in), static_cast<const float*>(in2),
+                                               ws, blocks, p->rb, 1.0f, lr)
+                     : launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
   const float b = inv_scale_2d(p), a = fwd_scale_2d(p);
   const float w_lin = weight * b, w_sq = weight * (b / a);
@@ -598,13 +606,56 @@ static int grad_impl(fftmi_plan* p, const void* in, const void* spectrum, const 
 
 int fft2d_filter_mask_grad(fft_plan_t p, const void* grad_y, const void* spectrum, float* grad_mask,
                            void* workspace, void* stream) {
-  return grad_impl(p, grad_y, spectrum, nullptr, 1.0f, grad_mask, workspace, stream);
+  return grad_impl(p, grad_y, nullptr, spectrum, nullptr, 1.0f, grad_mask, workspace, stream);
 }
 
-int fft2d_filter_mse_grad(fft_plan_t p, const void* resid, const void* spectrum, const float* mask, float weight,
-                          float* grad_mask, void* workspace, void* stream) {
+int fft2d_filter_mse_grad(fft_plan_t p, const void* x, const void* c, const void* spectrum, const float* mask,
+                          float weight, float* grad_mask, void* workspace, void* stream) {
   if (!mask && plan_live(p) && p->batch > 0) return FFT_ERR_ARG;
-  return grad_impl(p, resid, spectrum, mask, weight, grad_mask, workspace, stream);
+  return grad_impl(p, x, c, spectrum, mask, weight, grad_mask, workspace, stream);
+}
+
+int fft2d_filter_mse(fft_plan_t p, const float* x, const float* c, const float* mask, float weight, void* spectrum,
+                     float* loss, void* workspace, void* stream) {
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  if (p->kind != 2) return FFT_ERR_STATE;
+  if (p->padded || p->half || !(p->flags & FFT_IN_REAL_F32) || p->rb < 2) return FFT_ERR_UNSUPPORTED;
+  if (!loss) return FFT_ERR_ARG;
+  if (p->batch > 0 && (!x || !c || !mask || !spectrum)) return FFT_ERR_ARG;
+  if (!workspace) return FFT_ERR_WORKSPACE;
+  int rc = check_plan(p, nullptr);
+  if (rc != FFT_OK) return rc;
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  float2* ws = static_cast<float2*>(workspace);
+  float* part = reinterpret_cast<float*>(static_cast<char*>(workspace) + p->loss_off);
+  MaskArgs mk;
+  std::memset(&mk, 0, sizeof(mk));
+  mk.kind = FFT_MASK_TENSOR_F32;
+  mk.data = mask;
+  mk.tensor_bias = -1.0f;
+  mk.inv_n = 1.0f / (float)p->n;
+  mk.inv_m = 1.0f / (float)p->m;
+  Launch lr = launch_for(st, p->tables, p->log_m);
+  Launch lcn = launch_for(st, p->tables, p->log_n);
+  const int64_t plane = p->n * p->m;
+  int64_t nparts = 0;
+  for (int64_t b0 = 0; b0 < p->batch; b0 += p->chunk) {
+    const int64_t nb = std::min(p->chunk, p->batch - b0);
+    const int64_t blocks = nb * p->n / p->rb;
+    hipError_t e = launch_rows_to_blk(p->log_m, false, true, x + b0 * plane, true, ws, blocks, p->rb,
+                                      fwd_scale_2d(p), lr);
+    if (e != hipSuccess) return hip_fail(e);
+    e = launch_cols_filter(p->log_n, ws, static_cast<float2*>(spectrum) + b0 * plane, nb, (int)p->m, p->rb, p->w,
+                           false, mk, lcn);
+    if (e != hipSuccess) return hip_fail(e);
+    int64_t nt = 0;
+    e = launch_rows_loss(p->log_m, ws, x + b0 * plane, c + b0 * plane, part + nparts, blocks, p->rb, inv_scale_2d(p),
+                         &nt, lr);
+    if (e != hipSuccess) return hip_fail(e);
+    nparts += nt;
+  }
+  hipError_t e = launch_sum_partials(part, nparts, weight, loss, st);
+  return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 
 int fft_plan_destroy(fft_plan_t p) {

@@ -254,10 +254,10 @@ struct MaskEval<L, FFT_MASK_TENSOR_F32> {
   unsigned lane, qs;
   __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
       : col(mk.data + v), lane((unsigned)(j * M)), qs((unsigned)((L / elems_per_thread(L)) * M)) {}
-  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs&) const {
+  __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs& mk) const {
     const unsigned l = fresh(lane);
 #pragma unroll
-    for (int q = 0; q < elems_per_thread(L); ++q) a[q] = cscale(a[q], __ldg(col + l + q * qs));
+    for (int q = 0; q < elems_per_thread(L); ++q) a[q] = cscale(a[q], __ldg(col + l + q * qs) + mk.tensor_bias);
   }
 };
 

@@ -100,11 +100,15 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
 // HALF: only columns 0 .. L/2-1 are stored (blocks of L/2 columns), the
 // half spectrum that a real row determines.  Column 0 carries the two real
 // values A[0] and A[L/2] of a row as one complex number (A[0] + i A[L/2]).
-template <int L, bool INV, bool HALF>
+//
+// DIFF: the rows are in - in2 (the residual x - c of the fused MSE form),
+// formed as the two inputs are loaded.
+template <int L, bool INV, bool HALF, bool DIFF = false>
 __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* __restrict__ in,
                                                                    float2* __restrict__ ws, int rb, int npt,
                                                                    int ntiles, float scale,
-                                                                   const float2* __restrict__ tws) {
+                                                                   const float2* __restrict__ tws,
+                                                                   const float* __restrict__ in2 = nullptr) {
   static_assert(!HALF || !kSplitExchange, "half spectrum with whole complex LDS entries");
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT, RBY = lds_region_bytes(L, 1);
@@ -132,6 +136,14 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
     const unsigned l = fresh(lane_in);
 #pragma unroll
     for (int q = 0; q < E; ++q) d[q] = make_float2(ld_nt(b, l + q * TPT), ld_nt(b, l + L + q * TPT));
+    if constexpr (DIFF) {
+      const float* b2 = in2 + first_row(t) * L;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        d[q].x -= ld_nt(b2, l + q * TPT);
+        d[q].y -= ld_nt(b2, l + L + q * TPT);
+      }
+    }
   };
   int n = blockIdx.x;
   if (n < ntiles) load(a, (int)tile_of(n, ntiles));
@@ -377,6 +389,77 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
 #pragma unroll
     for (int q = 0; q < E; ++q) a[q] = nx[q];
   }
+}
+
+// Last pass of the fused filter + mean-squared-error forward (real images).
+// The workspace holds the column-filtered spectrum of (m - 1) X, so the
+// inverse row transform gives y - x; with the inputs x and c the tile's
+// elements of y - c = (y - x) + (x - c) are squared and summed, and the sum
+// goes to part[tile] (a fixed-order tree in LDS).  y is not written.
+template <int L>
+__global__ __launch_bounds__(Shape<L>::LB) void k_rows_loss(const float2* __restrict__ ws, const float* __restrict__ xin,
+                                                            const float* __restrict__ cin, float* __restrict__ part,
+                                                            int rb, int nt, int ntiles, float scale,
+                                                            const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT;
+  const int lnt = ilog2_pow2(nt), lsub = ilog2_pow2(rb / nt);
+  const int tid = threadIdx.x, sl = tid & (nt - 1), j = tid >> lnt;
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L>() + sl * lds_region_bytes(L, nt);
+  const unsigned lane_in = (unsigned)(j * rb + sl), lane_out = (unsigned)(sl * L + j);
+  const int qs = TPT * rb;
+  float* red = reinterpret_cast<float*>(regions<L>());
+  for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    float2 a[E];
+    {
+      const float2* b = ws + (int64_t)(t >> lsub) * L * rb + (t & ((1 << lsub) - 1)) * nt;
+      const unsigned f = fresh(lane_in);
+#pragma unroll
+      for (int q = 0; q < E; ++q) a[q] = ld(b, f + q * qs);
+    }
+    fft_reg<L, true, S::TWM>(a, j, x, tw);
+    const int64_t r0 = (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * nt;
+    float acc = 0.f;
+    {
+      const float* xb = xin + r0 * L;
+      const float* cb = cin + r0 * L;
+      const unsigned f = fresh(lane_out);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const float re = fmaf(a[q].x, scale, ld_nt(xb, f + q * TPT) - ld_nt(cb, f + q * TPT));
+        const float im = a[q].y * scale;
+        acc = fmaf(re, re, fmaf(im, im, acc));
+      }
+    }
+    lds_barrier();  // the transform's last LDS reads are done
+    red[tid] = acc;
+    lds_barrier();
+    for (int h = (int)blockDim.x >> 1; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      lds_barrier();
+    }
+    if (tid == 0) part[t] = red[0];
+    lds_barrier();  // red[0] read before the next tile's transform reuses LDS
+  }
+}
+
+// out[0] = weight * (part[0] + ... + part[n-1]), in double precision, in a
+// fixed order (one workgroup of 256 threads).
+__global__ __launch_bounds__(256) void k_sum_partials(const float* __restrict__ part, int64_t n, float weight,
+                                                      float* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)(red[0] * (double)weight);
 }
 
 // ============================================================== kernel C
@@ -911,8 +994,8 @@ int rows_per_tile(int rb, int target) {
 
 template <int LG>
 struct RowsToBlk {
-  static hipError_t run(bool inv, bool pair, bool half, const void* in, bool in_f32, float2* ws, int64_t blocks,
-                        int rb, float scale, const Launch& lc) {
+  static hipError_t run(bool inv, bool pair, bool half, const void* in, const void* in2, bool in_f32, float2* ws,
+                        int64_t blocks, int rb, float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const float2* tw = twiddle_src<L>(lc);
     if (pair && rb >= 2) {
@@ -922,16 +1005,20 @@ struct RowsToBlk {
         const int lds = tw_bytes<L>() + npt * lds_region_bytes(L, 1);
         const float* fin = static_cast<const float*>(in);
         const int64_t ntiles = blocks * (rb / 2 / npt);
+        if (in2)
+          return go(k_rows_to_blk_pair<L, false, false, true>, ntiles, npt * TPT, lds, lc.stream, fin, ws, rb, npt,
+                    (int)ntiles, scale, tw, static_cast<const float*>(in2));
         if constexpr (L >= 2) {
           if (half)
             return go(inv ? k_rows_to_blk_pair<L, true, true> : k_rows_to_blk_pair<L, false, true>, ntiles,
-                      npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw);
+                      npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw,
+                      static_cast<const float*>(nullptr));
         }
         return go(inv ? k_rows_to_blk_pair<L, true, false> : k_rows_to_blk_pair<L, false, false>, ntiles, npt * TPT,
-                  lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw);
+                  lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw, static_cast<const float*>(nullptr));
       }
     }
-    if (half) return hipErrorInvalidValue;
+    if (half || in2) return hipErrorInvalidValue;
     const int nt = rows_per_tile<L>(rb, 512);
     const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
     const int64_t ntiles = blocks * (rb / nt);
@@ -955,6 +1042,20 @@ struct RowsFromBlk {
     auto k = inv ? (out_f32 ? k_rows_from_blk<L, true, true> : k_rows_from_blk<L, true, false>)
                  : (out_f32 ? k_rows_from_blk<L, false, true> : k_rows_from_blk<L, false, false>);
     return go(k, ntiles, nt * TPT, lds, lc.stream, ws, out, rb, nt, (int)ntiles, scale, tw);
+  }
+};
+
+template <int LG>
+struct RowsLoss {
+  static hipError_t run(const float2* ws, const float* x, const float* c, float* part, int64_t blocks, int rb,
+                        float scale, int64_t* ntiles_out, const Launch& lc) {
+    constexpr int L = 1 << LG, TPT = threads_per_transform(L);
+    const int nt = rows_per_tile<L>(rb, 256);
+    const int lds = tw_bytes<L>() + std::max(nt * lds_region_bytes(L, nt), (int)(nt * TPT * sizeof(float)));
+    const int64_t ntiles = blocks * (rb / nt);
+    *ntiles_out = ntiles;
+    return go(k_rows_loss<L>, ntiles, nt * TPT, lds, lc.stream, ws, x, c, part, rb, nt, (int)ntiles, scale,
+              twiddle_src<L>(lc));
   }
 };
 
@@ -1077,7 +1178,10 @@ struct ColsStrided {
     return RowsRm<K>::run(inv, in, in_f32, out, out_f32, rows, scale, lc);
 #define FFTMI_CASE_RowsToBlk(K) \
   case K:                       \
-    return RowsToBlk<K>::run(inv, pair, half, in, in_f32, ws, blocks, rb, scale, lc);
+    return RowsToBlk<K>::run(inv, pair, half, in, in2, in_f32, ws, blocks, rb, scale, lc);
+#define FFTMI_CASE_RowsLoss(K) \
+  case K:                      \
+    return RowsLoss<K>::run(ws, x, c, part, blocks, rb, scale, ntiles, lc);
 #define FFTMI_CASE_RowsC2R(K) \
   case K:                     \
     return RowsC2R<K>::run(ws, out, out_f32, blocks, rb, scale, lc);
@@ -1105,13 +1209,32 @@ hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void
 hipError_t launch_rows_to_blk(int log2L, bool inv, bool pair, const void* in, bool in_f32, float2* ws,
                               int64_t blocks, int rb, float scale, const Launch& lc) {
   const bool half = false;
+  const void* in2 = nullptr;
+  FFTMI_DISPATCH(RowsToBlk, log2L)
+}
+
+hipError_t launch_rows_to_blk_diff(int log2L, const float* in, const float* in2, float2* ws, int64_t blocks, int rb,
+                                   float scale, const Launch& lc) {
+  if (rb < 2) return hipErrorInvalidValue;
+  const bool inv = false, pair = true, half = false, in_f32 = true;
   FFTMI_DISPATCH(RowsToBlk, log2L)
 }
 
 hipError_t launch_rows_to_blk_half(int log2L, const float* in, float2* ws, int64_t blocks, int rb, float scale,
                                    const Launch& lc) {
   const bool inv = false, pair = true, half = true, in_f32 = true;
+  const void* in2 = nullptr;
   FFTMI_DISPATCH(RowsToBlk, log2L)
+}
+
+hipError_t launch_rows_loss(int log2L, const float2* ws, const float* x, const float* c, float* part, int64_t blocks,
+                            int rb, float scale, int64_t* ntiles, const Launch& lc) {
+  FFTMI_DISPATCH(RowsLoss, log2L)
+}
+
+hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, part, n, weight, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_rows_c2r(int log2L, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,

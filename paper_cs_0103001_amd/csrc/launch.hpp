@@ -22,6 +22,7 @@ struct MaskArgs {
   double disc_b2;       // b^2
   double c1, c2;        // disc centre (bin units)
   float inv_n, inv_m;   // 1/N and 1/M (exact powers of two) for the frequency grid
+  float tensor_bias;    // added to every tensor-mask value (-1: the fused MSE form's m - 1)
 };
 
 struct Launch {
@@ -40,6 +41,19 @@ hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void
 // RB even).
 hipError_t launch_rows_to_blk(int log2L, bool inv, bool pair, const void* in, bool in_f32, float2* ws,
                               int64_t blocks, int rb, float scale, const Launch& lc);
+
+// Pass one of the fused MSE gradient: real rows in - in2 (pairs, rb even).
+hipError_t launch_rows_to_blk_diff(int log2L, const float* in, const float* in2, float2* ws, int64_t blocks, int rb,
+                                   float scale, const Launch& lc);
+
+// Last pass of the fused MSE forward: inverse row transforms of the blocked
+// workspace (the filtered spectrum of (m - 1) X), plus x - c, squared and
+// summed per tile into part[0 .. *ntiles).
+hipError_t launch_rows_loss(int log2L, const float2* ws, const float* x, const float* c, float* part, int64_t blocks,
+                            int rb, float scale, int64_t* ntiles, const Launch& lc);
+
+// out[0] = weight * sum of part[0 .. n), double precision, fixed order.
+hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float* out, hipStream_t st);
 
 // Half-spectrum path for real rows (pass one): rows in pairs, columns
 // 0 .. L/2-1 of each row's spectrum into blocks of L/2 columns, column 0

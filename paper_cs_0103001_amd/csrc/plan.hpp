@@ -52,8 +52,10 @@ struct fftmi_plan {
   const float2* tw_lo = nullptr;
   const float2* tw_hi = nullptr;
   size_t ws_bytes = 0, spec_bytes = 0;
-  // rank 2: image groups of the mask-gradient column pass
+  // rank 2: image groups of the mask-gradient column pass, and the workspace
+  // offset of the fused MSE forward's per-tile sums
   int grad_groups = 1;
+  size_t loss_off = 0;
   fftmi::RaggedState* ragged = nullptr;
 };
 

@@ -78,8 +78,9 @@ def test_calls_reject_bad_plans():
     assert lib.fft2d_filter(bogus, p, p, None, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_save(bogus, p, p, None, p, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_mask_grad(bogus, p, p, p, p, None) == B.FFT_ERR_ARG
-    assert lib.fft2d_filter_mse_grad(bogus, p, p, p, 1.0, p, p, None) == B.FFT_ERR_ARG
-    assert lib.fft2d_filter_mse_grad(None, p, p, p, 1.0, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mse_grad(bogus, p, p, p, p, 1.0, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mse_grad(None, p, None, p, p, 1.0, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mse(bogus, p, p, p, 1.0, p, p, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_ragged(bogus, p, p, None, p, None) == B.FFT_ERR_ARG
 
 
