@@ -289,6 +289,25 @@ def main():
         del noisy, clean, ol, wsl
 
     if not args.skip_extra:
+        # ------------------------------------------------------------ 1D sweep
+        # forward transforms of complex64 signals, 256 MiB per batch (2^25
+        # points), N = 2^10 .. 2^22; GB/s counts one read and one write of the
+        # batch (the passes beyond 2^14 read and write it twice)
+        xs = torch.randn(2 ** 25, dtype=torch.complex64, device=dev)
+        ys = torch.empty_like(xs)
+        sweep = {}
+        for lg in range(10, 23):
+            n1 = 1 << lg
+            p1 = api.get_plan(1, (n1,), 2 ** 25 // n1, 0, dev)
+            w1 = p1.workspace()
+            pp = [ctypes.c_void_p(t.data_ptr()) for t in (xs, ys, w1)]
+            ms1 = timed(torch, lambda: B.fft_exec(p1.h, pp[0], pp[1], pp[2], B.FFT_FORWARD, st), max(5, K // 5), 2)
+            sweep[str(lg)] = round(2 * (256 << 20) / (ms1 * 1e-3) / 1e9, 1)
+            del w1
+        result["sweep_1d"] = {"GB/s_by_log2N": sweep, "note": "forward, complex64, 2^25 points per batch; "
+                                                               "N > 2^14 takes two strided passes"}
+        del xs, ys
+
         # ------------------------------------------------------------- ragged
         sizes = synth.ragged_sizes()
         log("generating the ragged batch (%d images)" % len(sizes))
