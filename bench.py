@@ -29,7 +29,7 @@ N = M = 4096
 BUTTER = dict(kind="butterworth", cutoff=0.15, order=4)
 # algorithmic bytes per pixel of each pass of the plain path (f32 in, c64 out)
 PASS_BYTES = {0: 4 + 8, 1: 8 + 8, 2: 8 + 8}
-PASS_NAMES = {0: "rows_fwd (k_rows_to_blk_pair<4096, false, false>)", 1: "cols_filter (k_cols_filter<4096, 3, false>)",
+PASS_NAMES = {0: "rows_fwd (k_rows_to_blk_pair<4096, false, false, false>)", 1: "cols_filter (k_cols_filter<4096, 3, false>)",
               2: "rows_inv (k_rows_from_blk<4096, true, false>)"}
 
 
