@@ -229,6 +229,18 @@ int mask_args(const fft_mask* mk, const fftmi_plan* p, MaskArgs* out) { return f
 }  // namespace fftmi
 
 // =================================================================== C-ABI
+// Pad of the blocked layout's block stride (elements).  A stride that is a
+// multiple of 4 KiB puts the row blocks a column tile reads on the same
+// memory channels; 32 extra elements (256 bytes) spread them.  FFTMI_BLOCK_PAD
+// (a multiple of 32, up to 4096) overrides the pad for tuning.
+static int64_t block_pad(int64_t stride) {
+  if (const char* e = std::getenv("FFTMI_BLOCK_PAD")) {
+    const long v = std::atol(e);
+    if (v >= 0 && v <= 4096 && v % 32 == 0) return v;
+  }
+  return (stride * (int64_t)sizeof(float2)) % 4096 == 0 ? 32 : 0;
+}
+
 extern "C" {
 
 int fft_version(void) { return 0x000100; }
@@ -311,14 +323,16 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
     // columns the workspace carries: M, or 0 .. M/2 - 1 of a half spectrum
     const int64_t mc = p->half ? M / 2 : M;
     p->w = tuned_cols_width(p.get(), (int)mc);
+    p->bs = rb * mc + block_pad(rb * mc);
+    p->img = (N / rb) * p->bs;
     p->chunk = filter_chunk(N, mc, batch);
-    p->ws_bytes = (size_t)batch * (size_t)N * (size_t)mc * sizeof(float2);
+    p->ws_bytes = (size_t)batch * (size_t)p->img * sizeof(float2);
     p->spec_bytes = p->ws_bytes;
     // the mask gradient's per-group partial sums follow the blocked data
     p->grad_groups = grad_groups(M / p->w, batch);
     if (p->grad_groups > 1) {
-      p->ws_bytes = (p->ws_bytes + 255) & ~(size_t)255;
-      p->ws_bytes += (size_t)p->grad_groups * (size_t)N * (size_t)M * sizeof(float);
+      p->part_off = (p->ws_bytes + 255) & ~(size_t)255;
+      p->ws_bytes = p->part_off + (size_t)p->grad_groups * (size_t)N * (size_t)M * sizeof(float);
     }
     // then the fused MSE forward's per-tile loss sums (at most one per row)
     if (!p->half) {
@@ -381,12 +395,13 @@ int fft2d_spectrum(fft_plan_t p, const void* in, float* magnitude, void* workspa
   const int64_t blocks = p->batch * p->n / p->rb;
   const bool pair = in_f32 && p->rb >= 2;
   Launch lr = launch_for(st, p->tables, p->log_m);
-  e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
+  const unsigned bs = (unsigned)p->bs;
+  e = launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, bs, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
   Launch lcn = launch_for(st, p->tables, p->log_n);
-  e = launch_cols_fft(p->log_n, false, ws, p->batch, (int)p->m, p->rb, p->w, lcn);
+  e = launch_cols_fft(p->log_n, false, ws, p->batch, (int)p->m, p->rb, bs, p->w, lcn);
   if (e != hipSuccess) return hip_fail(e);
-  e = launch_unblock_mag(ws, magnitude, p->batch * p->n, (int)p->m, p->rb, fwd_scale_2d(p), st);
+  e = launch_unblock_mag(ws, magnitude, p->batch * p->n, (int)p->m, p->rb, bs, fwd_scale_2d(p), st);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 
@@ -452,12 +467,13 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
   const int64_t blocks = p->batch * p->n / p->rb;
   const bool pair = in_f32 && p->rb >= 2;
   Launch lr = launch_for(st, p->tables, p->log_m);
-  e = launch_rows_to_blk(p->log_m, inv_tw, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
+  const unsigned bs = (unsigned)p->bs;
+  e = launch_rows_to_blk(p->log_m, inv_tw, pair, in, in_f32, ws, blocks, p->rb, bs, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
   Launch lcn = launch_for(st, p->tables, p->log_n);
-  e = launch_cols_fft(p->log_n, inv_tw, ws, p->batch, (int)p->m, p->rb, p->w, lcn);
+  e = launch_cols_fft(p->log_n, inv_tw, ws, p->batch, (int)p->m, p->rb, bs, p->w, lcn);
   if (e != hipSuccess) return hip_fail(e);
-  e = launch_unblock(ws, out, out_f32, p->batch * p->n, (int)p->m, p->rb, scale, st);
+  e = launch_unblock(ws, out, out_f32, p->batch * p->n, (int)p->m, p->rb, bs, scale, st);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 
@@ -506,27 +522,28 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   // the whole batch.
   const int64_t plane = p->n * p->m;
   const int64_t mc = p->half ? p->m / 2 : p->m;  // workspace columns
+  const unsigned bs = (unsigned)p->bs;
   const int64_t chunk = stages == 7 ? p->chunk : p->batch;
   for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, p->batch - b0);
     const int64_t blocks = nb * p->n / p->rb;
     const char* cin = static_cast<const char*>(in) + (in ? b0 * plane * (in_f32 ? 4 : 8) : 0);
     char* cout = static_cast<char*>(out) + (out ? b0 * plane * (out_f32 ? 4 : 8) : 0);
-    float2* cspec = spectrum ? static_cast<float2*>(spectrum) + b0 * plane : nullptr;
+    float2* cspec = spectrum ? static_cast<float2*>(spectrum) + b0 * p->img : nullptr;
     hipError_t e = hipSuccess;
     if (stages & 1) {
       e = p->half ? launch_rows_to_blk_half(p->log_m, static_cast<const float*>(static_cast<const void*>(cin)), ws,
-                                            blocks, p->rb, fwd_scale_2d(p), lr)
-                  : launch_rows_to_blk(p->log_m, false, pair, cin, in_f32, ws, blocks, p->rb, fwd_scale_2d(p), lr);
+                                            blocks, p->rb, bs, fwd_scale_2d(p), lr)
+                  : launch_rows_to_blk(p->log_m, false, pair, cin, in_f32, ws, blocks, p->rb, bs, fwd_scale_2d(p), lr);
       if (e != hipSuccess) return hip_fail(e);
     }
     if (stages & 2) {
-      e = launch_cols_filter(p->log_n, ws, cspec, nb, (int)mc, p->rb, p->w, p->half, mk, lcn);
+      e = launch_cols_filter(p->log_n, ws, cspec, nb, (int)mc, p->rb, bs, p->w, p->half, mk, lcn);
       if (e != hipSuccess) return hip_fail(e);
     }
     if (stages & 4) {
-      e = p->half ? launch_rows_c2r(p->log_m, ws, cout, out_f32, blocks, p->rb, inv_scale_2d(p), lr)
-                  : launch_rows_from_blk(p->log_m, true, ws, cout, out_f32, blocks, p->rb, inv_scale_2d(p), lr);
+      e = p->half ? launch_rows_c2r(p->log_m, ws, cout, out_f32, blocks, p->rb, bs, inv_scale_2d(p), lr)
+                  : launch_rows_from_blk(p->log_m, true, ws, cout, out_f32, blocks, p->rb, bs, inv_scale_2d(p), lr);
       if (e != hipSuccess) return hip_fail(e);
     }
   }
@@ -581,21 +598,19 @@ static int grad_impl(fftmi_plan* p, const void* in, const void* in2, const void*
   Launch lr = launch_for(st, p->tables, p->log_m);
   // unscaled forward transform of the rows; the adjoint's scale goes into w_lin
   if (in2 && !pair) return FFT_ERR_UNSUPPORTED;
+  const unsigned bs = (unsigned)p->bs;
   hipError_t e = in2 ? launch_rows_to_blk_diff(p->log_m, static_cast<const float*>(in), static_cast<const float*>(in2),
-                                               ws, blocks, p->rb, 1.0f, lr)
-                     : launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, 1.0f, lr);
+                                               ws, blocks, p->rb, bs, 1.0f, lr)
+                     : launch_rows_to_blk(p->log_m, false, pair, in, in_f32, ws, blocks, p->rb, bs, 1.0f, lr);
   if (e != hipSuccess) return hip_fail(e);
   const float b = inv_scale_2d(p), a = fwd_scale_2d(p);
   const float w_lin = weight * b, w_sq = weight * (b / a);
   const int groups = p->grad_groups;
   float* part = grad_mask;
-  if (groups > 1) {
-    const size_t off = ((size_t)p->batch * (size_t)p->n * (size_t)p->m * sizeof(float2) + 255) & ~(size_t)255;
-    part = reinterpret_cast<float*>(static_cast<char*>(workspace) + off);
-  }
+  if (groups > 1) part = reinterpret_cast<float*>(static_cast<char*>(workspace) + p->part_off);
   Launch lcn = launch_for(st, p->tables, p->log_n);
   e = launch_cols_grad(p->log_n, ws, static_cast<const float2*>(spectrum), mask, part, p->batch, groups, (int)p->m,
-                       p->rb, p->w, w_lin, w_sq, lcn);
+                       p->rb, bs, p->w, w_lin, w_sq, lcn);
   if (e != hipSuccess) return hip_fail(e);
   if (groups > 1) {
     e = launch_sum_groups(part, grad_mask, p->n * p->m, groups, st);
@@ -642,15 +657,16 @@ int fft2d_filter_mse(fft_plan_t p, const float* x, const float* c, const float* 
   for (int64_t b0 = 0; b0 < p->batch; b0 += p->chunk) {
     const int64_t nb = std::min(p->chunk, p->batch - b0);
     const int64_t blocks = nb * p->n / p->rb;
-    hipError_t e = launch_rows_to_blk(p->log_m, false, true, x + b0 * plane, true, ws, blocks, p->rb,
+    const unsigned bs = (unsigned)p->bs;
+    hipError_t e = launch_rows_to_blk(p->log_m, false, true, x + b0 * plane, true, ws, blocks, p->rb, bs,
                                       fwd_scale_2d(p), lr);
     if (e != hipSuccess) return hip_fail(e);
-    e = launch_cols_filter(p->log_n, ws, static_cast<float2*>(spectrum) + b0 * plane, nb, (int)p->m, p->rb, p->w,
-                           false, mk, lcn);
+    e = launch_cols_filter(p->log_n, ws, static_cast<float2*>(spectrum) + b0 * p->img, nb, (int)p->m, p->rb, bs,
+                           p->w, false, mk, lcn);
     if (e != hipSuccess) return hip_fail(e);
     int64_t nt = 0;
-    e = launch_rows_loss(p->log_m, ws, x + b0 * plane, c + b0 * plane, part + nparts, blocks, p->rb, inv_scale_2d(p),
-                         &nt, lr);
+    e = launch_rows_loss(p->log_m, ws, x + b0 * plane, c + b0 * plane, part + nparts, blocks, p->rb, bs,
+                         inv_scale_2d(p), &nt, lr);
     if (e != hipSuccess) return hip_fail(e);
     nparts += nt;
   }

@@ -315,7 +315,22 @@ enum TwMode {
   kTwGlobal = 0,  // loaded from the global tables at every stage
   kTwLds = 1,     // loaded from an LDS copy of the tables
   kTwReg = 2,     // held in registers for the kernel's whole run
+  kTwMix = 3,     // small stage tables (NS <= 16) in LDS, the rest in registers
 };
+
+// kTwMix: stage s >= 1 reads its factors from LDS when its table is small
+// (stride NS <= 16: at most 15 x 16 entries, 1920 bytes), so that the
+// registers hold only the factors of the long-stride stages.  NS grows with
+// s, so the LDS stages are a prefix 1 .. mix_lds_end(L) - 1.
+FFTMI_HD constexpr bool mix_in_lds(int L, int s) { return stage_ns(L, s) <= 16; }
+FFTMI_HD constexpr int mix_lds_end(int L) {
+  int s = 1;
+  while (s < num_stages(L) && mix_in_lds(L, s)) ++s;
+  return s;
+}
+// LDS entries of the small tables (LDS layout of lds_tw_offset).
+FFTMI_HD constexpr int mix_lds_entries(int L) { return lds_tw_offset(L, mix_lds_end(L)); }
+FFTMI_HD constexpr int mix_lds_bytes(int L) { return mix_lds_entries(L) > 0 ? ((mix_lds_entries(L) * 8 + 255) / 256) * 256 : 0; }
 
 // Register-held twiddles: all stages s >= 1 of one thread, in stage order.
 template <int L>
@@ -342,6 +357,41 @@ __device__ __forceinline__ void load_twiddles_reg(float2 (&twr)[reg_tw_count<L>(
   }
 }
 
+// kTwMix: register offsets count only the stages kept in registers.
+template <int L>
+__host__ __device__ constexpr int reg_tw_offset_mix(int s) {
+  int off = 0;
+  for (int i = mix_lds_end(L); i < s; ++i) off += (elems_per_thread(L) / stage_radix(L, i)) * (stage_radix(L, i) - 1);
+  return off;
+}
+template <int L>
+__host__ __device__ constexpr int reg_tw_count_mix() {
+  return reg_tw_offset_mix<L>(num_stages(L)) > 0 ? reg_tw_offset_mix<L>(num_stages(L)) : 1;
+}
+
+// kTwMix set-up: thread j's register factors of the long-stride stages, and
+// the workgroup's LDS copy of the small tables, rearranged from the global
+// layout [k][r] to the LDS layout [r-1][k] (entries (r-1)*NS + k).  The
+// first exchange's barriers order the copy before any read.
+template <int L, int S = mix_lds_end(L)>
+__device__ __forceinline__ void load_twiddles_reg_mix(float2 (&twr)[reg_tw_count_mix<L>()], int j,
+                                                      const float2* __restrict__ blob) {
+  if constexpr (S < num_stages(L)) {
+    stage_twiddles<L, S>(twr + reg_tw_offset_mix<L>(S), j, blob);
+    load_twiddles_reg_mix<L, S + 1>(twr, j, blob);
+  }
+}
+template <int L, int S = 1>
+__device__ __forceinline__ void load_twiddles_lds_mix(float2* twl, const float2* __restrict__ blob, int tid, int nthr) {
+  if constexpr (S < mix_lds_end(L)) {
+    constexpr int NS = stage_ns(L, S), R = stage_radix(L, S), n = NS * (R - 1);
+    const float2* src = blob + tw_stage_offset(L, S);
+    float2* dst = twl + lds_tw_offset(L, S);
+    for (int i = tid; i < n; i += nthr) dst[i] = __ldg(src + (i % NS) * R + i / NS + 1);
+    load_twiddles_lds_mix<L, S + 1>(twl, blob, tid, nthr);
+  }
+}
+
 template <int L, int S, bool INV, int TWM>
 struct StageChain {
   __device__ __forceinline__ static void run(float2 (&a)[elems_per_thread(L)], int j, void* x,
@@ -350,6 +400,16 @@ struct StageChain {
       if constexpr (TWM == kTwReg) {
         exchange<L, S>(a, j, x);
         stage_compute<L, S, INV>(a, tws + reg_tw_offset<L>(S));
+      } else if constexpr (TWM == kTwMix && !mix_in_lds(L, S)) {
+        exchange<L, S>(a, j, x);
+        stage_compute<L, S, INV>(a, tws + reg_tw_offset_mix<L>(S));
+      } else if constexpr (TWM == kTwMix) {
+        // the small tables sit at the start of the workgroup's dynamic LDS
+        extern __shared__ float4 lds_raw[];
+        float2 tw[StageInfo<L, S>::NTW > 0 ? StageInfo<L, S>::NTW : 1];
+        exchange<L, S>(a, j, x);
+        stage_twiddles_lds<L, S>(tw, j, reinterpret_cast<const float2*>(lds_raw));
+        stage_compute<L, S, INV>(a, tw);
       } else {
         float2 tw[StageInfo<L, S>::NTW > 0 ? StageInfo<L, S>::NTW : 1];
         if constexpr (TWM == kTwLds) {

@@ -18,9 +18,35 @@ __device__ __forceinline__ char* lds_base() {
   return reinterpret_cast<char*>(lds_raw);
 }
 
+// Twiddle source of the single-pass kernels (lengths up to 2^12): small
+// stage tables in LDS, the long-stride stages' factors in registers.
 #ifndef FFTMI_TWM
-#define FFTMI_TWM 2
+#define FFTMI_TWM 3
 #endif
+
+// Software prefetch of the next tile into registers (persistent kernels of
+// the 2D path), per pass: the row pass into the blocked layout, the column
+// pass, the row pass out of it.  Without it a kernel uses fewer registers and
+// relies on more resident workgroups per CU to overlap memory and arithmetic:
+// at 4096 points the column pass and the last row pass fit four workgroups
+// per CU (the LDS limit) without it, three or fewer with it, and run faster
+// so; the first row pass (two transforms per workgroup) is faster with it.
+#ifndef FFTMI_PF_ROWS_IN
+#define FFTMI_PF_ROWS_IN 1
+#endif
+#ifndef FFTMI_PF_COLS
+#define FFTMI_PF_COLS 0
+#endif
+#ifndef FFTMI_PF_ROWS_OUT
+#define FFTMI_PF_ROWS_OUT 0
+#endif
+enum { kPassRowsIn = 0, kPassCols = 1, kPassRowsOut = 2 };
+template <int L, int PASS>
+struct Prefetch {
+  static constexpr bool on = L > 0 && (PASS == kPassRowsIn ? FFTMI_PF_ROWS_IN != 0
+                                       : PASS == kPassCols ? FFTMI_PF_COLS != 0
+                                                           : FFTMI_PF_ROWS_OUT != 0);
+};
 
 template <int L>
 struct Shape {
@@ -33,12 +59,14 @@ struct Shape {
   // Twiddles: in registers up to 2^12 points (30 complex values per thread),
   // from the global tables beyond.
   static constexpr int TWM = L <= (1 << kLdsTwMaxLog2) ? FFTMI_TWM : kTwGlobal;
-  static constexpr int TWB = TWM == kTwLds ? lds_tw_bytes(L) : 0;  // LDS bytes they take
+  static constexpr int TWB = TWM == kTwLds ? lds_tw_bytes(L) : (TWM == kTwMix ? mix_lds_bytes(L) : 0);  // LDS bytes
 };
 
 // A kernel's twiddle factors for thread index j: a register array loaded
-// once (kTwReg), an LDS copy made by the whole workgroup (kTwLds), or the
-// global tables (kTwGlobal).  The host passes the matching table layout.
+// once (kTwReg), an LDS copy made by the whole workgroup (kTwLds), both
+// (kTwMix: small tables in LDS, the long-stride stages in registers), or the
+// global tables (kTwGlobal).  The host passes the matching table layout
+// (the global layout for kTwMix).
 template <int L, int M = Shape<L>::TWM>
 struct Twiddles {
   const float2* p;
@@ -60,6 +88,17 @@ template <int L>
 struct Twiddles<L, kTwReg> {
   float2 r[reg_tw_count<L>()];
   __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int j) { load_twiddles_reg<L>(r, j, src); }
+  __device__ __forceinline__ const float2* ptr() const { return r; }
+};
+
+template <int L>
+struct Twiddles<L, kTwMix> {
+  float2 r[reg_tw_count_mix<L>()];
+  __device__ __forceinline__ Twiddles(const float2* __restrict__ src, int j) {
+    extern __shared__ float4 lds_raw[];
+    load_twiddles_lds_mix<L>(reinterpret_cast<float2*>(lds_raw), src, threadIdx.x, blockDim.x);
+    load_twiddles_reg_mix<L>(r, j, src);
+  }
   __device__ __forceinline__ const float2* ptr() const { return r; }
 };
 

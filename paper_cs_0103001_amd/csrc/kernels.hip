@@ -105,8 +105,8 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
 // formed as the two inputs are loaded.
 template <int L, bool INV, bool HALF, bool DIFF = false>
 __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* __restrict__ in,
-                                                                   float2* __restrict__ ws, int rb, int npt,
-                                                                   int ntiles, float scale,
+                                                                   float2* __restrict__ ws, int rb, unsigned bs,
+                                                                   int npt, int ntiles, float scale,
                                                                    const float2* __restrict__ tws,
                                                                    const float* __restrict__ in2 = nullptr) {
   static_assert(!HALF || !kSplitExchange, "half spectrum with whole complex LDS entries");
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
   const unsigned lane_out = (unsigned)(v0 * np + pp);
   const char* xs = reg + pp * RBY;
   const float h = 0.5f * scale;
-  float2 a[E], nx[E];
+  float2 a[E], nx[Prefetch<L, kPassRowsIn>::on ? E : 1];
   auto first_row = [&](int t) __attribute__((always_inline)) {
     return (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * 2 * npt;
   };
@@ -146,15 +146,20 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
     }
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
-  settle(a);
+  if constexpr (Prefetch<L, kPassRowsIn>::on) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+    settle(a);
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    if constexpr (Prefetch<L, kPassRowsIn>::on) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, t);
+    }
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
     // float4 base of this tile: block start plus the tile's first pair
-    constexpr int LC = HALF ? L / 2 : L;  // stored columns
-    float4* dst = reinterpret_cast<float4*>(ws + (int64_t)(t >> lsub) * LC * rb) + (t & ((1 << lsub) - 1)) * npt;
+    float4* dst = reinterpret_cast<float4*>(ws + (int64_t)(t >> lsub) * bs) + (t & ((1 << lsub) - 1)) * npt;
     const unsigned lo = fresh(lane_out);
     if constexpr (kSplitExchange) {
       float ax[E], by[E];
@@ -197,8 +202,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
         dst[lo + i * TPT * np] = o;
       }
     }
+    if constexpr (Prefetch<L, kPassRowsIn>::on) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = nx[q];
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
   }
 }
 
@@ -210,7 +217,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
 // float4 (Y1(v), Y2(v)) and staged through LDS.
 template <int L, bool F32>
 __global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __restrict__ ws, void* __restrict__ out,
-                                                                int rb, int npt, int ntiles, float scale,
+                                                                int rb, unsigned bs, int npt, int ntiles, float scale,
                                                                 const float2* __restrict__ tws) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT, RBY = lds_region_bytes(L, 1), H = L / 2, EH = E / 2;
@@ -226,7 +233,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __
   float4 a[EH], nx[EH];
   auto pair_of = [&](int t) __attribute__((always_inline)) { return (t & ((1 << lsub) - 1)) * npt + p; };
   auto load = [&](float4(&d)[EH], int t) __attribute__((always_inline)) {
-    const float4* b = reinterpret_cast<const float4*>(ws + (int64_t)(t >> lsub) * H * rb) + pair_of(t);
+    const float4* b = reinterpret_cast<const float4*>(ws + (int64_t)(t >> lsub) * bs) + pair_of(t);
     const unsigned l = fresh(lane);
 #pragma unroll
     for (int q = 0; q < EH; ++q) d[q] = ld(b, l + q * TPT * np);
@@ -288,7 +295,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __
 // (rows g*rb + sub*nt ...); lanes interleave those nt rows.
 template <int L, bool INV>
 __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk(const void* __restrict__ in, int in_f32, float2* __restrict__ ws,
-                                                      int rb, int nt, int ntiles, float scale,
+                                                      int rb, unsigned bs, int nt, int ntiles, float scale,
                                                       const float2* __restrict__ tws) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
@@ -299,11 +306,11 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk(const void* __rest
   char* x = regions<L>() + sl * lds_region_bytes(L, nt);
   const unsigned lane_in = (unsigned)(sl * L + j), lane_out = (unsigned)(j * rb + sl);
   const int qs = TPT * rb;
-  // first row of tile t; its block starts at element (t >> lsub) * rb * L
+  // first row of tile t; its block starts at element (t >> lsub) * bs
   auto row0 = [&](int t) __attribute__((always_inline)) {
     return (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * nt;
   };
-  float2 a[E], nx[E];
+  float2 a[E], nx[Prefetch<L, kPassRowsIn>::on ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
     if (in_f32) {
       const float* b = static_cast<const float*>(in) + row0(t) * L;
@@ -322,20 +329,28 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk(const void* __rest
     }
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
-  settle(a);
+  if constexpr (Prefetch<L, kPassRowsIn>::on) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+    settle(a);
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    if constexpr (Prefetch<L, kPassRowsIn>::on) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, t);
+    }
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
-    float2* b = ws + (int64_t)(t >> lsub) * L * rb + (t & ((1 << lsub) - 1)) * nt;
+    float2* b = ws + (int64_t)(t >> lsub) * bs + (t & ((1 << lsub) - 1)) * nt;
     {
       const unsigned f_lane_out = fresh(lane_out);
 #pragma unroll
       for (int q = 0; q < E; ++q) b[f_lane_out + q * qs] = cscale(a[q], scale);
     }
+    if constexpr (Prefetch<L, kPassRowsIn>::on) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = nx[q];
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
   }
 }
 
@@ -343,7 +358,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk(const void* __rest
 // Row pass out of the blocked layout into row-major output; tiles as above.
 template <int L, bool INV, bool F32>
 __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __restrict__ ws, void* __restrict__ out,
-                                                                int rb, int nt, int ntiles, float scale,
+                                                                int rb, unsigned bs, int nt, int ntiles, float scale,
                                                                 const float2* __restrict__ tws) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
@@ -354,9 +369,9 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
   char* x = regions<L>() + sl * lds_region_bytes(L, nt);
   const unsigned lane_in = (unsigned)(j * rb + sl), lane_out = (unsigned)(sl * L + j);
   const int qs = TPT * rb;
-  float2 a[E], nx[E];
+  float2 a[E], nx[Prefetch<L, kPassRowsOut>::on ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
-    const float2* b = ws + (int64_t)(t >> lsub) * L * rb + (t & ((1 << lsub) - 1)) * nt;
+    const float2* b = ws + (int64_t)(t >> lsub) * bs + (t & ((1 << lsub) - 1)) * nt;
     {
       const unsigned f_lane_in = fresh(lane_in);
 #pragma unroll
@@ -364,11 +379,17 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
     }
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
-  settle(a);
+  if constexpr (Prefetch<L, kPassRowsOut>::on) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+    settle(a);
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    if constexpr (Prefetch<L, kPassRowsOut>::on) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, t);
+    }
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
     const int64_t r0 = (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * nt;
     if constexpr (F32) {
@@ -386,8 +407,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
         for (int q = 0; q < E; ++q) st_nt(&b[f_lane_out + q * TPT], cscale(a[q], scale));
       }
     }
+    if constexpr (Prefetch<L, kPassRowsOut>::on) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = nx[q];
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
   }
 }
 
@@ -399,7 +422,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
 template <int L>
 __global__ __launch_bounds__(Shape<L>::LB) void k_rows_loss(const float2* __restrict__ ws, const float* __restrict__ xin,
                                                             const float* __restrict__ cin, float* __restrict__ part,
-                                                            int rb, int nt, int ntiles, float scale,
+                                                            int rb, unsigned bs, int nt, int ntiles, float scale,
                                                             const float2* __restrict__ tws) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
@@ -415,7 +438,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_loss(const float2* __rest
     const int t = (int)tile_of(n, ntiles);
     float2 a[E];
     {
-      const float2* b = ws + (int64_t)(t >> lsub) * L * rb + (t & ((1 << lsub) - 1)) * nt;
+      const float2* b = ws + (int64_t)(t >> lsub) * bs + (t & ((1 << lsub) - 1)) * nt;
       const unsigned f = fresh(lane_in);
 #pragma unroll
       for (int q = 0; q < E; ++q) a[q] = ld(b, f + q * qs);
@@ -478,7 +501,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const float* __restrict__ 
 // transformed back.
 template <int L, int MK, bool HALF>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict__ ws, float2* __restrict__ save, int M,
-                                                      int rb, int w, int ltiles, int ntiles, MaskArgs mk,
+                                                      int rb, unsigned bs, int w, int ltiles, int ntiles, MaskArgs mk,
                                                       const float2* __restrict__ tws) {
   static_assert(!HALF || (!kSplitExchange && MK != FFT_MASK_TENSOR_F32), "half spectrum: analytic masks");
   using S = Shape<L>;
@@ -487,23 +510,30 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
   const Twiddles<L> twd(tws, ln.j);
   const float2* tw = twd.ptr();
   char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
-  const unsigned qs = (unsigned)(TPT * M);
-  const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
+  const unsigned qs = (unsigned)(TPT / rb) * bs;
+  const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
+  const int64_t img = (int64_t)(L / rb) * bs;
   const int tmask = (1 << ltiles) - 1;
-  float2 a[E], nx[E];
+  float2 a[E], nx[Prefetch<L, kPassCols>::on ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
-    const float2* b = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    const float2* b = ws + (int64_t)(t >> ltiles) * img + (t & tmask) * w * rb;
     const unsigned f_lane = fresh(lane);
 #pragma unroll
     for (int q = 0; q < E; ++q) d[q] = b[f_lane + q * qs];
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
-  settle(a);
+  if constexpr (Prefetch<L, kPassCols>::on) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+    settle(a);
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
-    float2* base = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    if constexpr (Prefetch<L, kPassCols>::on) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, t);
+    }
+    float2* base = ws + (int64_t)(t >> ltiles) * img + (t & tmask) * w * rb;
     const int v = (t & tmask) * w + ln.c;
     fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
     if (save) {
@@ -551,46 +581,57 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
 #pragma unroll
       for (int q = 0; q < E; ++q) base[f_lane + q * qs] = a[q];
     }
+    if constexpr (Prefetch<L, kPassCols>::on) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = nx[q];
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
   }
 }
 
 // One column transform of the blocked layout, in place (unscaled).
 template <int L, bool INV>
-__global__ __launch_bounds__(Shape<L>::LB) void k_cols_fft(float2* __restrict__ ws, int M, int rb, int w, int ltiles,
-                                                           int ntiles, const float2* __restrict__ tws) {
+__global__ __launch_bounds__(Shape<L>::LB) void k_cols_fft(float2* __restrict__ ws, int M, int rb, unsigned bs, int w,
+                                                           int ltiles, int ntiles, const float2* __restrict__ tws) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
   const Twiddles<L> twd(tws, ln.j);
   const float2* tw = twd.ptr();
   char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
-  const unsigned qs = (unsigned)(TPT * M);
-  const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
+  const unsigned qs = (unsigned)(TPT / rb) * bs;
+  const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
+  const int64_t img = (int64_t)(L / rb) * bs;
   const int tmask = (1 << ltiles) - 1;
-  float2 a[E], nx[E];
+  float2 a[E], nx[Prefetch<L, kPassCols>::on ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
-    const float2* b = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    const float2* b = ws + (int64_t)(t >> ltiles) * img + (t & tmask) * w * rb;
     const unsigned f_lane = fresh(lane);
 #pragma unroll
     for (int q = 0; q < E; ++q) d[q] = b[f_lane + q * qs];
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
-  settle(a);
+  if constexpr (Prefetch<L, kPassCols>::on) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+    settle(a);
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    if constexpr (Prefetch<L, kPassCols>::on) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, t);
+    }
     fft_reg<L, INV, S::TWM>(a, ln.j, x, tw);
-    float2* b = ws + (int64_t)(t >> ltiles) * L * M + (t & tmask) * w * rb;
+    float2* b = ws + (int64_t)(t >> ltiles) * img + (t & tmask) * w * rb;
     {
       const unsigned f_lane = fresh(lane);
 #pragma unroll
       for (int q = 0; q < E; ++q) b[f_lane + q * qs] = a[q];
     }
+    if constexpr (Prefetch<L, kPassCols>::on) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = nx[q];
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
   }
 }
 
@@ -600,12 +641,12 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_fft(float2* __restrict__ 
 // stores covers 64 consecutive elements of one row.
 template <int RB, bool F32>
 __global__ __launch_bounds__(256) void k_unblock(const float2* __restrict__ ws, void* __restrict__ out, int M,
-                                                 int64_t items, float scale) {
+                                                 unsigned bs, int64_t items, float scale) {
   const int lm = ilog2_pow2(M);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t blk = i >> lm;
     const int v = (int)(i & (M - 1));
-    const float2* src = ws + (blk * M + v) * RB;
+    const float2* src = ws + blk * bs + v * RB;
     float2 a[RB];
 #pragma unroll
     for (int s = 0; s < RB; ++s) a[s] = __ldg(src + s);
@@ -651,12 +692,12 @@ __global__ __launch_bounds__(256) void k_crop(const T* __restrict__ in, T* __res
 // magnitude), laid out like k_unblock's output.
 template <int RB>
 __global__ __launch_bounds__(256) void k_unblock_mag(const float2* __restrict__ ws, float* __restrict__ out, int M,
-                                                     int64_t items, float scale) {
+                                                     unsigned bs, int64_t items, float scale) {
   const int lm = ilog2_pow2(M);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < items; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t blk = i >> lm;
     const int v = (int)(i & (M - 1));
-    const float2* src = ws + (blk * M + v) * RB;
+    const float2* src = ws + blk * bs + v * RB;
     float* dst = out + blk * RB * M + v;
 #pragma unroll
     for (int s = 0; s < RB; ++s) {
@@ -678,7 +719,8 @@ __global__ __launch_bounds__(256) void k_unblock_mag(const float2* __restrict__ 
 template <int L, bool MT>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __restrict__ ws, const float2* __restrict__ save,
                                                             const float* __restrict__ mask, float* __restrict__ part,
-                                                            int nimg, int per_group, int M, int rb, int w, int ltiles,
+                                                            int nimg, int per_group, int M, int rb, unsigned bs,
+                                                            int w, int ltiles,
                                                             int ntiles, float w_lin, float w_sq,
                                                             const float2* __restrict__ tws) {
   using S = Shape<L>;
@@ -687,10 +729,11 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
   const Twiddles<L> twd(tws, ln.j);
   const float2* tw = twd.ptr();
   char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
-  const unsigned qs = (unsigned)(TPT * M);
-  const unsigned lane = (unsigned)(ln.jh * M * rb + ln.c * rb + ln.s);
+  const unsigned qs = (unsigned)(TPT / rb) * bs;        // blocked layout, rows j + q*TPT
+  const unsigned qs_out = (unsigned)(TPT * M);           // row-major mask and partial sums
+  const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
   const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
-  const int64_t plane = (int64_t)L * M;
+  const int64_t plane = (int64_t)(L / rb) * bs;
   const int tmask = (1 << ltiles) - 1;
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
@@ -734,10 +777,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
       const float* mrow = mask + ct * w;
 #pragma unroll
       for (int q = 0; q < E; ++q)
-        dst[f_lane_out + q * qs] = fmaf(w_sq * (ld(mrow, f_lane_out + q * qs) - 1.0f), acc2[q], w_lin * acc[q]);
+        dst[f_lane_out + q * qs_out] = fmaf(w_sq * (ld(mrow, f_lane_out + q * qs_out) - 1.0f), acc2[q], w_lin * acc[q]);
     } else {
 #pragma unroll
-      for (int q = 0; q < E; ++q) dst[f_lane_out + q * qs] = w_lin * acc[q];
+      for (int q = 0; q < E; ++q) dst[f_lane_out + q * qs_out] = w_lin * acc[q];
     }
   }
 }
@@ -995,7 +1038,7 @@ int rows_per_tile(int rb, int target) {
 template <int LG>
 struct RowsToBlk {
   static hipError_t run(bool inv, bool pair, bool half, const void* in, const void* in2, bool in_f32, float2* ws,
-                        int64_t blocks, int rb, float scale, const Launch& lc) {
+                        int64_t blocks, int rb, unsigned bs, float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const float2* tw = twiddle_src<L>(lc);
     if (pair && rb >= 2) {
@@ -1006,16 +1049,16 @@ struct RowsToBlk {
         const float* fin = static_cast<const float*>(in);
         const int64_t ntiles = blocks * (rb / 2 / npt);
         if (in2)
-          return go(k_rows_to_blk_pair<L, false, false, true>, ntiles, npt * TPT, lds, lc.stream, fin, ws, rb, npt,
-                    (int)ntiles, scale, tw, static_cast<const float*>(in2));
+          return go(k_rows_to_blk_pair<L, false, false, true>, ntiles, npt * TPT, lds, lc.stream, fin, ws, rb, bs,
+                    npt, (int)ntiles, scale, tw, static_cast<const float*>(in2));
         if constexpr (L >= 2) {
           if (half)
             return go(inv ? k_rows_to_blk_pair<L, true, true> : k_rows_to_blk_pair<L, false, true>, ntiles,
-                      npt * TPT, lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw,
+                      npt * TPT, lds, lc.stream, fin, ws, rb, bs, npt, (int)ntiles, scale, tw,
                       static_cast<const float*>(nullptr));
         }
         return go(inv ? k_rows_to_blk_pair<L, true, false> : k_rows_to_blk_pair<L, false, false>, ntiles, npt * TPT,
-                  lds, lc.stream, fin, ws, rb, npt, (int)ntiles, scale, tw, static_cast<const float*>(nullptr));
+                  lds, lc.stream, fin, ws, rb, bs, npt, (int)ntiles, scale, tw, static_cast<const float*>(nullptr));
       }
     }
     if (half || in2) return hipErrorInvalidValue;
@@ -1023,17 +1066,17 @@ struct RowsToBlk {
     const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
     const int64_t ntiles = blocks * (rb / nt);
     if (inv)
-      return go(k_rows_to_blk<L, true>, ntiles, nt * TPT, lds, lc.stream, in, (int)in_f32, ws, rb, nt, (int)ntiles,
-                scale, tw);
-    return go(k_rows_to_blk<L, false>, ntiles, nt * TPT, lds, lc.stream, in, (int)in_f32, ws, rb, nt, (int)ntiles,
-              scale, tw);
+      return go(k_rows_to_blk<L, true>, ntiles, nt * TPT, lds, lc.stream, in, (int)in_f32, ws, rb, bs, nt,
+                (int)ntiles, scale, tw);
+    return go(k_rows_to_blk<L, false>, ntiles, nt * TPT, lds, lc.stream, in, (int)in_f32, ws, rb, bs, nt,
+              (int)ntiles, scale, tw);
   }
 };
 
 template <int LG>
 struct RowsFromBlk {
-  static hipError_t run(bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
-                        const Launch& lc) {
+  static hipError_t run(bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, unsigned bs,
+                        float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const float2* tw = twiddle_src<L>(lc);
     const int nt = rows_per_tile<L>(rb, 256);
@@ -1041,27 +1084,27 @@ struct RowsFromBlk {
     const int64_t ntiles = blocks * (rb / nt);
     auto k = inv ? (out_f32 ? k_rows_from_blk<L, true, true> : k_rows_from_blk<L, true, false>)
                  : (out_f32 ? k_rows_from_blk<L, false, true> : k_rows_from_blk<L, false, false>);
-    return go(k, ntiles, nt * TPT, lds, lc.stream, ws, out, rb, nt, (int)ntiles, scale, tw);
+    return go(k, ntiles, nt * TPT, lds, lc.stream, ws, out, rb, bs, nt, (int)ntiles, scale, tw);
   }
 };
 
 template <int LG>
 struct RowsLoss {
   static hipError_t run(const float2* ws, const float* x, const float* c, float* part, int64_t blocks, int rb,
-                        float scale, int64_t* ntiles_out, const Launch& lc) {
+                        unsigned bs, float scale, int64_t* ntiles_out, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int nt = rows_per_tile<L>(rb, 256);
     const int lds = tw_bytes<L>() + std::max(nt * lds_region_bytes(L, nt), (int)(nt * TPT * sizeof(float)));
     const int64_t ntiles = blocks * (rb / nt);
     *ntiles_out = ntiles;
-    return go(k_rows_loss<L>, ntiles, nt * TPT, lds, lc.stream, ws, x, c, part, rb, nt, (int)ntiles, scale,
+    return go(k_rows_loss<L>, ntiles, nt * TPT, lds, lc.stream, ws, x, c, part, rb, bs, nt, (int)ntiles, scale,
               twiddle_src<L>(lc));
   }
 };
 
 template <int LG>
 struct RowsC2R {
-  static hipError_t run(const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
+  static hipError_t run(const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, unsigned bs, float scale,
                         const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     if constexpr (L < 2) {
@@ -1073,7 +1116,7 @@ struct RowsC2R {
       if (lds > kLdsBytes || npt * TPT > max_block<L>()) return hipErrorInvalidValue;
       const int64_t ntiles = blocks * (rb / 2 / npt);
       return go(out_f32 ? k_rows_c2r_pair<L, true> : k_rows_c2r_pair<L, false>, ntiles, npt * TPT, lds, lc.stream, ws,
-                out, rb, npt, (int)ntiles, scale, twiddle_src<L>(lc));
+                out, rb, bs, npt, (int)ntiles, scale, twiddle_src<L>(lc));
     }
   }
 };
@@ -1081,8 +1124,8 @@ struct RowsC2R {
 template <int LG>
 struct ColsFilter {
   template <bool HALF>
-  static hipError_t launch(float2* ws, float2* save, int64_t nimg, int M, int rb, int w, const MaskArgs& mk,
-                           const Launch& lc) {
+  static hipError_t launch(float2* ws, float2* save, int64_t nimg, int M, int rb, unsigned bs, int w,
+                           const MaskArgs& mk, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = M / w;
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
@@ -1092,31 +1135,32 @@ struct ColsFilter {
     switch (mk.kind) {
       case FFT_MASK_TENSOR_F32:
         if constexpr (HALF) return hipErrorInvalidValue;
-        return go(k_cols_filter<L, FFT_MASK_TENSOR_F32, false>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        return go(k_cols_filter<L, FFT_MASK_TENSOR_F32, false>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, bs, w, lt,
                   (int)ntiles, mk, tw);
       case FFT_MASK_GAUSSIAN:
-        return go(k_cols_filter<L, FFT_MASK_GAUSSIAN, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        return go(k_cols_filter<L, FFT_MASK_GAUSSIAN, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, bs, w, lt,
                   (int)ntiles, mk, tw);
       case FFT_MASK_BUTTERWORTH:
-        return go(k_cols_filter<L, FFT_MASK_BUTTERWORTH, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w,
+        return go(k_cols_filter<L, FFT_MASK_BUTTERWORTH, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, bs, w,
                   lt, (int)ntiles, mk, tw);
       case FFT_MASK_DISC:
-        return go(k_cols_filter<L, FFT_MASK_DISC, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        return go(k_cols_filter<L, FFT_MASK_DISC, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, bs, w, lt,
                   (int)ntiles, mk, tw);
       default:
-        return go(k_cols_filter<L, FFT_MASK_NONE, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, w, lt,
+        return go(k_cols_filter<L, FFT_MASK_NONE, HALF>, ntiles, w * TPT, lds, lc.stream, ws, save, M, rb, bs, w, lt,
                   (int)ntiles, mk, tw);
     }
   }
-  static hipError_t run(float2* ws, float2* save, int64_t nimg, int M, int rb, int w, bool half, const MaskArgs& mk,
-                        const Launch& lc) {
-    return half ? launch<true>(ws, save, nimg, M, rb, w, mk, lc) : launch<false>(ws, save, nimg, M, rb, w, mk, lc);
+  static hipError_t run(float2* ws, float2* save, int64_t nimg, int M, int rb, unsigned bs, int w, bool half,
+                        const MaskArgs& mk, const Launch& lc) {
+    return half ? launch<true>(ws, save, nimg, M, rb, bs, w, mk, lc)
+                : launch<false>(ws, save, nimg, M, rb, bs, w, mk, lc);
   }
 };
 
 template <int LG>
 struct ColsFft {
-  static hipError_t run(bool inv, float2* ws, int64_t nimg, int M, int rb, int w, const Launch& lc) {
+  static hipError_t run(bool inv, float2* ws, int64_t nimg, int M, int rb, unsigned bs, int w, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = M / w;
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
@@ -1124,14 +1168,14 @@ struct ColsFft {
     const int64_t ntiles = nimg * tiles;
     const int lt = ilog2c(tiles);
     auto k = inv ? k_cols_fft<L, true> : k_cols_fft<L, false>;
-    return go(k, ntiles, w * TPT, lds, lc.stream, ws, M, rb, w, lt, (int)ntiles, tw);
+    return go(k, ntiles, w * TPT, lds, lc.stream, ws, M, rb, bs, w, lt, (int)ntiles, tw);
   }
 };
 
 template <int LG>
 struct ColsGrad {
   static hipError_t run(const float2* ws, const float2* save, const float* mask, float* part, int64_t nimg,
-                        int groups, int M, int rb, int w, float w_lin, float w_sq, const Launch& lc) {
+                        int groups, int M, int rb, unsigned bs, int w, float w_lin, float w_sq, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
     const int ctiles = M / w;
@@ -1140,9 +1184,9 @@ struct ColsGrad {
     const int lt = ilog2c(ctiles);
     if (mask)
       return go(k_cols_grad<L, true>, ntiles, w * TPT, lds, lc.stream, ws, save, mask, part, (int)nimg, per_group,
-                M, rb, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
+                M, rb, bs, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
     return go(k_cols_grad<L, false>, ntiles, w * TPT, lds, lc.stream, ws, save, mask, part, (int)nimg, per_group, M,
-              rb, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
+              rb, bs, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
   }
 };
 
@@ -1178,25 +1222,25 @@ struct ColsStrided {
     return RowsRm<K>::run(inv, in, in_f32, out, out_f32, rows, scale, lc);
 #define FFTMI_CASE_RowsToBlk(K) \
   case K:                       \
-    return RowsToBlk<K>::run(inv, pair, half, in, in2, in_f32, ws, blocks, rb, scale, lc);
+    return RowsToBlk<K>::run(inv, pair, half, in, in2, in_f32, ws, blocks, rb, bs, scale, lc);
 #define FFTMI_CASE_RowsLoss(K) \
   case K:                      \
-    return RowsLoss<K>::run(ws, x, c, part, blocks, rb, scale, ntiles, lc);
+    return RowsLoss<K>::run(ws, x, c, part, blocks, rb, bs, scale, ntiles, lc);
 #define FFTMI_CASE_RowsC2R(K) \
   case K:                     \
-    return RowsC2R<K>::run(ws, out, out_f32, blocks, rb, scale, lc);
+    return RowsC2R<K>::run(ws, out, out_f32, blocks, rb, bs, scale, lc);
 #define FFTMI_CASE_RowsFromBlk(K) \
   case K:                         \
-    return RowsFromBlk<K>::run(inv, ws, out, out_f32, blocks, rb, scale, lc);
+    return RowsFromBlk<K>::run(inv, ws, out, out_f32, blocks, rb, bs, scale, lc);
 #define FFTMI_CASE_ColsFilter(K) \
   case K:                        \
-    return ColsFilter<K>::run(ws, save, nimg, M, rb, w, half, mask, lc);
+    return ColsFilter<K>::run(ws, save, nimg, M, rb, bs, w, half, mask, lc);
 #define FFTMI_CASE_ColsFft(K) \
   case K:                     \
-    return ColsFft<K>::run(inv, ws, nimg, M, rb, w, lc);
+    return ColsFft<K>::run(inv, ws, nimg, M, rb, bs, w, lc);
 #define FFTMI_CASE_ColsGrad(K) \
   case K:                      \
-    return ColsGrad<K>::run(ws, save, mask, part, nimg, groups, M, rb, w, w_lin, w_sq, lc);
+    return ColsGrad<K>::run(ws, save, mask, part, nimg, groups, M, rb, bs, w, w_lin, w_sq, lc);
 #define FFTMI_CASE_ColsStrided(K) \
   case K:                         \
     return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_lo, tw_hi, h, lc);
@@ -1207,28 +1251,28 @@ hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void
 }
 
 hipError_t launch_rows_to_blk(int log2L, bool inv, bool pair, const void* in, bool in_f32, float2* ws,
-                              int64_t blocks, int rb, float scale, const Launch& lc) {
+                              int64_t blocks, int rb, unsigned bs, float scale, const Launch& lc) {
   const bool half = false;
   const void* in2 = nullptr;
   FFTMI_DISPATCH(RowsToBlk, log2L)
 }
 
 hipError_t launch_rows_to_blk_diff(int log2L, const float* in, const float* in2, float2* ws, int64_t blocks, int rb,
-                                   float scale, const Launch& lc) {
+                                   unsigned bs, float scale, const Launch& lc) {
   if (rb < 2) return hipErrorInvalidValue;
   const bool inv = false, pair = true, half = false, in_f32 = true;
   FFTMI_DISPATCH(RowsToBlk, log2L)
 }
 
-hipError_t launch_rows_to_blk_half(int log2L, const float* in, float2* ws, int64_t blocks, int rb, float scale,
-                                   const Launch& lc) {
+hipError_t launch_rows_to_blk_half(int log2L, const float* in, float2* ws, int64_t blocks, int rb, unsigned bs,
+                                   float scale, const Launch& lc) {
   const bool inv = false, pair = true, half = true, in_f32 = true;
   const void* in2 = nullptr;
   FFTMI_DISPATCH(RowsToBlk, log2L)
 }
 
 hipError_t launch_rows_loss(int log2L, const float2* ws, const float* x, const float* c, float* part, int64_t blocks,
-                            int rb, float scale, int64_t* ntiles, const Launch& lc) {
+                            int rb, unsigned bs, float scale, int64_t* ntiles, const Launch& lc) {
   FFTMI_DISPATCH(RowsLoss, log2L)
 }
 
@@ -1237,22 +1281,23 @@ hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float
   return hipGetLastError();
 }
 
-hipError_t launch_rows_c2r(int log2L, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
-                           const Launch& lc) {
+hipError_t launch_rows_c2r(int log2L, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, unsigned bs,
+                           float scale, const Launch& lc) {
   FFTMI_DISPATCH(RowsC2R, log2L)
 }
 
 hipError_t launch_rows_from_blk(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks,
-                                int rb, float scale, const Launch& lc) {
+                                int rb, unsigned bs, float scale, const Launch& lc) {
   FFTMI_DISPATCH(RowsFromBlk, log2L)
 }
 
-hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w, bool half,
-                              const MaskArgs& mask, const Launch& lc) {
+hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, unsigned bs, int w,
+                              bool half, const MaskArgs& mask, const Launch& lc) {
   FFTMI_DISPATCH(ColsFilter, log2L)
 }
 
-hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, int w, const Launch& lc) {
+hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, unsigned bs, int w,
+                           const Launch& lc) {
   FFTMI_DISPATCH(ColsFft, log2L)
 }
 
@@ -1286,26 +1331,27 @@ hipError_t launch_crop(const void* in, void* out, bool f32, int64_t nimg, int n0
   return hipGetLastError();
 }
 
-hipError_t launch_unblock_mag(const float2* ws, float* out, int64_t rows, int M, int rb, float scale, hipStream_t st) {
+hipError_t launch_unblock_mag(const float2* ws, float* out, int64_t rows, int M, int rb, unsigned bs, float scale,
+                              hipStream_t st) {
   if (rows % rb || (M & (M - 1))) return hipErrorInvalidValue;
   const int64_t items = rows / rb * M;
   if (items == 0) return hipSuccess;
   const dim3 g = elementwise_grid(items), b(256);
   switch (rb) {
     case 1:
-      hipLaunchKernelGGL(k_unblock_mag<1>, g, b, 0, st, ws, out, M, items, scale);
+      hipLaunchKernelGGL(k_unblock_mag<1>, g, b, 0, st, ws, out, M, bs, items, scale);
       break;
     case 2:
-      hipLaunchKernelGGL(k_unblock_mag<2>, g, b, 0, st, ws, out, M, items, scale);
+      hipLaunchKernelGGL(k_unblock_mag<2>, g, b, 0, st, ws, out, M, bs, items, scale);
       break;
     case 4:
-      hipLaunchKernelGGL(k_unblock_mag<4>, g, b, 0, st, ws, out, M, items, scale);
+      hipLaunchKernelGGL(k_unblock_mag<4>, g, b, 0, st, ws, out, M, bs, items, scale);
       break;
     case 8:
-      hipLaunchKernelGGL(k_unblock_mag<8>, g, b, 0, st, ws, out, M, items, scale);
+      hipLaunchKernelGGL(k_unblock_mag<8>, g, b, 0, st, ws, out, M, bs, items, scale);
       break;
     case 16:
-      hipLaunchKernelGGL(k_unblock_mag<16>, g, b, 0, st, ws, out, M, items, scale);
+      hipLaunchKernelGGL(k_unblock_mag<16>, g, b, 0, st, ws, out, M, bs, items, scale);
       break;
     default:
       return hipErrorInvalidValue;
@@ -1313,8 +1359,8 @@ hipError_t launch_unblock_mag(const float2* ws, float* out, int64_t rows, int M,
   return hipGetLastError();
 }
 
-hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, float scale,
-                          hipStream_t st) {
+hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, unsigned bs,
+                          float scale, hipStream_t st) {
   if (rows % rb || (M & (M - 1))) return hipErrorInvalidValue;
   const int64_t items = rows / rb * M;
   if (items == 0) return hipSuccess;
@@ -1323,9 +1369,9 @@ hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t row
 #define FFTMI_UNBLOCK(R)                                                                                   \
   if (rb == R) {                                                                                           \
     if (out_f32)                                                                                           \
-      hipLaunchKernelGGL((k_unblock<R, true>), g, b, 0, st, ws, out, M, items, scale);                     \
+      hipLaunchKernelGGL((k_unblock<R, true>), g, b, 0, st, ws, out, M, bs, items, scale);                     \
     else                                                                                                   \
-      hipLaunchKernelGGL((k_unblock<R, false>), g, b, 0, st, ws, out, M, items, scale);                    \
+      hipLaunchKernelGGL((k_unblock<R, false>), g, b, 0, st, ws, out, M, bs, items, scale);                    \
     return hipGetLastError();                                                                              \
   }
   FFTMI_UNBLOCK(1)
@@ -1338,7 +1384,7 @@ hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t row
 }
 
 hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, const float* mask, float* part,
-                            int64_t nimg, int groups, int M, int rb, int w, float w_lin, float w_sq,
+                            int64_t nimg, int groups, int M, int rb, unsigned bs, int w, float w_lin, float w_sq,
                             const Launch& lc) {
   FFTMI_DISPATCH(ColsGrad, log2L)
 }

@@ -2,10 +2,12 @@
 //
 // Layouts used between passes of the 2D path:
 //   row-major   image b, element (u, v) at  b*N*M + u*M + v
-//   blocked     image b, element (u, v) at  b*N*M + ((u / RB) * M + v) * RB + u % RB
+//   blocked     image b, element (u, v) at  (b*(N/RB) + u/RB) * BS + v*RB + u % RB
 // RB rows are interleaved per column so that a column tile of W columns reads
 // W*RB*8 contiguous bytes per row block, while a row pass over one block reads
-// and writes RB*M*8 contiguous bytes.
+// and writes RB*M*8 contiguous bytes.  The block stride BS is RB*M plus a
+// small pad (a multiple of 32 elements), so that the strided accesses of a
+// column tile do not all fall on the same memory channels.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -40,17 +42,17 @@ hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void
 // length L.  pair = pack two real rows into one complex transform (in_f32 and
 // RB even).
 hipError_t launch_rows_to_blk(int log2L, bool inv, bool pair, const void* in, bool in_f32, float2* ws,
-                              int64_t blocks, int rb, float scale, const Launch& lc);
+                              int64_t blocks, int rb, unsigned bs, float scale, const Launch& lc);
 
 // Pass one of the fused MSE gradient: real rows in - in2 (pairs, rb even).
 hipError_t launch_rows_to_blk_diff(int log2L, const float* in, const float* in2, float2* ws, int64_t blocks, int rb,
-                                   float scale, const Launch& lc);
+                                   unsigned bs, float scale, const Launch& lc);
 
 // Last pass of the fused MSE forward: inverse row transforms of the blocked
 // workspace (the filtered spectrum of (m - 1) X), plus x - c, squared and
 // summed per tile into part[0 .. *ntiles).
 hipError_t launch_rows_loss(int log2L, const float2* ws, const float* x, const float* c, float* part, int64_t blocks,
-                            int rb, float scale, int64_t* ntiles, const Launch& lc);
+                            int rb, unsigned bs, float scale, int64_t* ntiles, const Launch& lc);
 
 // out[0] = weight * sum of part[0 .. n), double precision, fixed order.
 hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float* out, hipStream_t st);
@@ -58,36 +60,38 @@ hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float
 // Half-spectrum path for real rows (pass one): rows in pairs, columns
 // 0 .. L/2-1 of each row's spectrum into blocks of L/2 columns, column 0
 // holding A[0] + i A[L/2].  rb even.
-hipError_t launch_rows_to_blk_half(int log2L, const float* in, float2* ws, int64_t blocks, int rb, float scale,
-                                   const Launch& lc);
+hipError_t launch_rows_to_blk_half(int log2L, const float* in, float2* ws, int64_t blocks, int rb, unsigned bs,
+                                   float scale, const Launch& lc);
 
 // Half-spectrum path, last pass: inverse row transforms of the blocked half
 // spectra (two rows per complex transform) into real rows (float32, or
 // complex64 with zero imaginary parts).  rb even.
-hipError_t launch_rows_c2r(int log2L, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, float scale,
-                           const Launch& lc);
+hipError_t launch_rows_c2r(int log2L, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, unsigned bs,
+                           float scale, const Launch& lc);
 
 // Row pass out of the blocked layout into row-major output.
 hipError_t launch_rows_from_blk(int log2L, bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks,
-                                int rb, float scale, const Launch& lc);
+                                int rb, unsigned bs, float scale, const Launch& lc);
 
 // Column pass on the blocked layout (column length L = N): forward transform,
 // mask multiply, inverse transform, in place.  save != nullptr also stores the
 // forward spectrum (blocked layout).  half: the workspace holds M columns of a
 // half spectrum (see launch_rows_to_blk_half; analytic masks only).
-hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, int w, bool half,
-                              const MaskArgs& mask, const Launch& lc);
+hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg, int M, int rb, unsigned bs, int w,
+                              bool half, const MaskArgs& mask, const Launch& lc);
 
 // Column pass on the blocked layout: one unscaled transform, in place.
-hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, int w, const Launch& lc);
+hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, unsigned bs, int w,
+                           const Launch& lc);
 
 // Blocked workspace (rows rows in blocks of rb) -> row-major out, times scale;
 // complex64 or, with out_f32, the real parts.
-hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, float scale,
-                          hipStream_t st);
+hipError_t launch_unblock(const float2* ws, void* out, bool out_f32, int64_t rows, int M, int rb, unsigned bs,
+                          float scale, hipStream_t st);
 
 // |z| * scale of the blocked workspace into row-major float32.
-hipError_t launch_unblock_mag(const float2* ws, float* out, int64_t rows, int M, int rb, float scale, hipStream_t st);
+hipError_t launch_unblock_mag(const float2* ws, float* out, int64_t rows, int M, int rb, unsigned bs, float scale,
+                              hipStream_t st);
 
 // Zero padding [nimg][n0][m0] -> [nimg][2^log2N][2^log2M] and cropping back
 // (float32 or complex64 elements).
@@ -102,7 +106,7 @@ hipError_t launch_crop(const void* in, void* out, bool f32, int64_t nimg, int n0
 // accumulate the real part; part[g] = w_lin * sum + (mask ? w_sq * (m - 1) *
 // sum |X|^2 : 0).  With groups == 1, part may be the final gradient.
 hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, const float* mask, float* part,
-                            int64_t nimg, int groups, int M, int rb, int w, float w_lin, float w_sq,
+                            int64_t nimg, int groups, int M, int rb, unsigned bs, int w, float w_lin, float w_sq,
                             const Launch& lc);
 
 // grad = sum over g of part[g] (n floats each, n % 4 == 0), in group order.

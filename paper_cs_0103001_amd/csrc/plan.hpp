@@ -34,8 +34,10 @@ struct fftmi_plan {
   uint32_t flags = 0;
   int log_n = 0, log_m = 0;
   fftmi::DevTables* tables = nullptr;
-  // rank 2: rows per block of the blocked layout, column tile width
+  // rank 2: rows per block of the blocked layout, column tile width, block
+  // stride in elements (rb * columns + pad) and elements per image
   int rb = 1, w = 1;
+  int64_t bs = 0, img = 0;
   // rank 2: images per chunk of fft2d_filter (passes run chunk by chunk)
   int64_t chunk = 1;
   // rank 2 made by fft_plan_padded: the callers' image size n0 x m0 (zero
@@ -53,9 +55,9 @@ struct fftmi_plan {
   const float2* tw_hi = nullptr;
   size_t ws_bytes = 0, spec_bytes = 0;
   // rank 2: image groups of the mask-gradient column pass, and the workspace
-  // offset of the fused MSE forward's per-tile sums
+  // offsets of their partial sums and of the fused MSE forward's per-tile sums
   int grad_groups = 1;
-  size_t loss_off = 0;
+  size_t part_off = 0, loss_off = 0;
   fftmi::RaggedState* ragged = nullptr;
 };
 
