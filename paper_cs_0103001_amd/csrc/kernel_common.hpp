@@ -152,6 +152,27 @@ __device__ __forceinline__ void st_nt(float2* p, float2 v) {
   __builtin_nontemporal_store(w, reinterpret_cast<fftmi_f2v*>(p));
 }
 
+// Buffer-resource access to one image of the blocked workspace.  The image's
+// base and byte size sit in a resource descriptor (SGPRs), the thread's fixed
+// byte offset in one VGPR, and the per-tile and per-element byte offsets in
+// an SGPR, so an access needs no vector-ALU address arithmetic.  The hardware
+// checks the offsets against the size: an access outside the image reads
+// zero and writes nothing instead of faulting.  Sizes must be below 4 GiB
+// (an image of at most 2^14 x 2^14 complex64 values is 2 GiB plus padding).
+typedef int fftmi_i2v __attribute__((ext_vector_type(2)));
+struct BlkBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ BlkBuf(const float2* base, uint64_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(base), (short)0, (int)(uint32_t)bytes,
+                                            0x00020000)) {}
+  __device__ __forceinline__ float2 ld(unsigned voff, unsigned soff) const {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  __device__ __forceinline__ void st(float2 v, unsigned voff, unsigned soff) const {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(fftmi_i2v, v), r, voff, soff, 0);
+  }
+};
+
 // A lane offset made opaque where it is used: the per-element offsets
 // lane + q*stride are then computed next to the access instead of being
 // hoisted out of the tile loop and held in registers for its whole length.
@@ -224,12 +245,23 @@ struct MaskEval<L, FFT_MASK_BUTTERWORTH> {
     fv2 = fv * fv;
   }
   __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs& mk) const {
+    // the order is uniform: one branch around straight-line code for the
+    // usual order 4 (exponent 8), the general power otherwise
+    if (mk.order == 4) {
 #pragma unroll
-    for (int q = 0; q < elems_per_thread(L); ++q) {
-      const float fu = row_freq<L>(fj, q);
-      const float qq = fmaf(fu, fu, fv2) * mk.inv_fc2;
-      const float p = (mk.order == 4) ? (qq * qq) * (qq * qq) : powi_pos(qq, mk.order);
-      a[q] = cscale(a[q], __builtin_amdgcn_rcpf(1.0f + p));
+      for (int q = 0; q < elems_per_thread(L); ++q) {
+        const float fu = row_freq<L>(fj, q);
+        const float qq = fmaf(fu, fu, fv2) * mk.inv_fc2;
+        const float q2 = qq * qq;
+        a[q] = cscale(a[q], __builtin_amdgcn_rcpf(fmaf(q2, q2, 1.0f)));
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < elems_per_thread(L); ++q) {
+        const float fu = row_freq<L>(fj, q);
+        const float qq = fmaf(fu, fu, fv2) * mk.inv_fc2;
+        a[q] = cscale(a[q], __builtin_amdgcn_rcpf(1.0f + powi_pos(qq, mk.order)));
+      }
     }
   }
   __device__ __forceinline__ float value(int, int q, const MaskArgs& mk) const {

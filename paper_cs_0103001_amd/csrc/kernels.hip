@@ -510,16 +510,18 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
   const Twiddles<L> twd(tws, ln.j);
   const float2* tw = twd.ptr();
   char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
-  const unsigned qs = (unsigned)(TPT / rb) * bs;
-  const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
+  // byte offsets: the thread's within a tile (VGPR), element q's and the
+  // tile's within the image (SGPR)
+  const unsigned qs8 = (unsigned)(TPT / rb) * bs * 8u;
+  const unsigned vlane = ((unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s)) * 8u;
   const int64_t img = (int64_t)(L / rb) * bs;
   const int tmask = (1 << ltiles) - 1;
   float2 a[E], nx[Prefetch<L, kPassCols>::on ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
-    const float2* b = ws + (int64_t)(t >> ltiles) * img + (t & tmask) * w * rb;
-    const unsigned f_lane = fresh(lane);
+    const BlkBuf b(ws + (int64_t)(t >> ltiles) * img, (uint64_t)img * 8u);
+    const unsigned toff = (unsigned)((t & tmask) * w * rb) * 8u;
 #pragma unroll
-    for (int q = 0; q < E; ++q) d[q] = b[f_lane + q * qs];
+    for (int q = 0; q < E; ++q) d[q] = b.ld(vlane, toff + q * qs8);
   };
   int n = blockIdx.x;
   if constexpr (Prefetch<L, kPassCols>::on) {
@@ -533,16 +535,14 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
     } else {
       load(a, t);
     }
-    float2* base = ws + (int64_t)(t >> ltiles) * img + (t & tmask) * w * rb;
+    const BlkBuf out(ws + (int64_t)(t >> ltiles) * img, (uint64_t)img * 8u);
+    const unsigned toff = (unsigned)((t & tmask) * w * rb) * 8u;
     const int v = (t & tmask) * w + ln.c;
     fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
     if (save) {
-      float2* sb = save + (base - ws);
-      {
-        const unsigned f_lane = fresh(lane);
+      const BlkBuf sb(save + (int64_t)(t >> ltiles) * img, (uint64_t)img * 8u);
 #pragma unroll
-        for (int q = 0; q < E; ++q) sb[f_lane + q * qs] = a[q];
-      }
+      for (int q = 0; q < E; ++q) sb.st(a[q], vlane, toff + q * qs8);
     }
     const int mfreq = HALF ? 2 * M : M;  // columns of the frequency grid
     if constexpr (HALF) {
@@ -576,11 +576,8 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
       me.apply(a, ln.j, mk);
     }
     fft_reg<L, true, S::TWM>(a, ln.j, x, tw);
-    {
-      const unsigned f_lane = fresh(lane);
 #pragma unroll
-      for (int q = 0; q < E; ++q) base[f_lane + q * qs] = a[q];
-    }
+    for (int q = 0; q < E; ++q) out.st(a[q], vlane, toff + q * qs8);
     if constexpr (Prefetch<L, kPassCols>::on) {
 #pragma unroll
       for (int q = 0; q < E; ++q) a[q] = nx[q];
