@@ -233,7 +233,7 @@ int mask_args(const fft_mask* mk, const fftmi_plan* p, MaskArgs* out) { return f
 // multiple of 4 KiB puts the row blocks a column tile reads on the same
 // memory channels; 32 extra elements (256 bytes) spread them.  FFTMI_BLOCK_PAD
 // (a multiple of 32, up to 4096) overrides the pad for tuning.
-static int64_t block_pad(int64_t stride) {
+int64_t fftmi::block_pad(int64_t stride) {
   if (const char* e = std::getenv("FFTMI_BLOCK_PAD")) {
     const long v = std::atol(e);
     if (v >= 0 && v <= 4096 && v % 32 == 0) return v;
@@ -323,7 +323,7 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
     // columns the workspace carries: M, or 0 .. M/2 - 1 of a half spectrum
     const int64_t mc = p->half ? M / 2 : M;
     p->w = tuned_cols_width(p.get(), (int)mc);
-    p->bs = rb * mc + block_pad(rb * mc);
+    p->bs = rb * mc + fftmi::block_pad(rb * mc);
     p->img = (N / rb) * p->bs;
     p->chunk = filter_chunk(N, mc, batch);
     p->ws_bytes = (size_t)batch * (size_t)p->img * sizeof(float2);

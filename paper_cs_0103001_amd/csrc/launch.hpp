@@ -138,13 +138,14 @@ inline int64_t persistent_grid(int64_t ntiles, int64_t resident) {
 constexpr int kRaggedMaxLog2 = 11;  // sides 1 .. 2048
 
 // One image of a ragged batch: element offset in the packed input/output and
-// in the workspace, log2 of its side and the rows per block of its blocked
-// workspace layout.
+// in the workspace, log2 of its side, the rows per block of its blocked
+// workspace layout and that layout's block stride (elements).
 struct RaggedImage {
   int64_t off;
   int64_t ws_off;
   int lg;
   int rb;
+  int64_t bs;
 };
 
 // FP32 twiddle tables (global layout) per log2 side.

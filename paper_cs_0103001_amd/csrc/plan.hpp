@@ -68,6 +68,10 @@ void plan_register(fftmi_plan* p);
 bool plan_live(const fftmi_plan* p);
 void plan_unregister(fftmi_plan* p);
 
+// Pad (elements) added to a blocked layout's block stride of `stride`
+// elements: 32 when the stride is a multiple of 4 KiB, else 0.
+int64_t block_pad(int64_t stride);
+
 // Widest power-of-two column tile (<= wmax, <= cols) that fits one workgroup.
 int widest_cols_tile(int log2L, int cols, int wmax);
 

@@ -49,7 +49,8 @@ struct RaggedRun {  // one run of images: the tile range of each pass
 struct RaggedState {
   std::vector<int64_t> sizes;
   std::vector<RaggedImage> imgs;
-  int64_t total = 0;  // sum of s^2
+  int64_t total = 0;     // sum of s^2
+  int64_t ws_total = 0;  // workspace elements (blocked layouts with padded strides)
   RaggedSchedule sched;
   std::vector<RaggedRun> runs;
   RaggedImage* d_imgs = nullptr;
@@ -69,6 +70,9 @@ struct RaggedState {
 namespace {
 
 int rb_for(int64_t s) { return (int)std::min<int64_t>(4, threads_per_transform((int)s)); }
+// block stride and workspace elements of one image of side s
+int64_t bs_for(int64_t s) { return rb_for(s) * s + block_pad(rb_for(s) * s); }
+int64_t ws_elems_for(int64_t s) { return (s / rb_for(s)) * bs_for(s); }
 
 void drop_graph(RaggedState* r) {
   if (r->exec) (void)hipGraphExecDestroy(r->exec);
@@ -94,9 +98,9 @@ int build_lists(RaggedState* r) {
   r->imgs.assign(n, RaggedImage{});
   // runs of consecutive images
   std::vector<std::pair<int64_t, int64_t>> spans;  // [first, last)
-  int64_t first = 0, bytes = 0, off = 0;
+  int64_t first = 0, bytes = 0, off = 0, ws_off = 0;
   for (int64_t i = 0; i < n; ++i) {
-    const int64_t s = r->sizes[i], b = s * s * 8;
+    const int64_t s = r->sizes[i], b = ws_elems_for(s) * 8;
     if (r->sched.chunk > 0 && i > first && bytes + b > r->sched.chunk) {
       spans.push_back({first, i});
       first = i;
@@ -104,11 +108,13 @@ int build_lists(RaggedState* r) {
     }
     RaggedImage& im = r->imgs[i];
     im.off = off;
-    im.ws_off = r->sched.chunk > 0 ? bytes / 8 : off;
+    im.ws_off = r->sched.chunk > 0 ? bytes / 8 : ws_off;
     im.lg = ilog2c((int)s);
     im.rb = rb_for(s);
+    im.bs = bs_for(s);
     bytes += b;
     off += s * s;
+    ws_off += ws_elems_for(s);
   }
   if (n > first) spans.push_back({first, n});
   std::vector<int2> lists[3];
@@ -323,7 +329,10 @@ int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32
   int rc = device_tables(dev, &p->tables);
   if (rc != FFT_OK) return rc;
   r->sizes.assign(sizes, sizes + count);
-  for (int64_t s : r->sizes) r->total += s * s;
+  for (int64_t s : r->sizes) {
+    r->total += s * s;
+    r->ws_total += ws_elems_for(s);
+  }
   for (int lg = 0; lg <= kRaggedMaxLog2; ++lg) r->tw.p[lg] = blob_for(p->tables, lg);
   if (const char* g = std::getenv("FFTMI_RAGGED_GRAPH")) r->use_graph = std::atoi(g) != 0;
   e = hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking);
@@ -337,7 +346,7 @@ int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32
     r.release();
     return rc;
   }
-  p->ws_bytes = (size_t)std::max<int64_t>(r->total, 1) * sizeof(float2);
+  p->ws_bytes = (size_t)std::max<int64_t>(r->ws_total, 1) * sizeof(float2);
   r.release();
   plan_register(p.get());
   *out = p.release();

@@ -10,9 +10,10 @@
 // Twiddles come from the global FP32 tables of each length (one per side).
 //
 // Image i of side s occupies elements [off, off + s*s) of the packed input
-// and output (row-major) and [ws_off, ws_off + s*s) of the workspace, where it
-// is kept in the blocked layout ((u / rb) * s + v) * rb + u % rb with
-// rb = min(4, TPT(s)), as in the uniform-batch passes.
+// and output (row-major) and (s / rb) * bs elements from ws_off in the
+// workspace, where it is kept in the blocked layout (u / rb) * bs + v * rb +
+// u % rb with rb = min(4, TPT(s)) and the padded block stride bs, as in the
+// uniform-batch passes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -56,7 +57,7 @@ __device__ __forceinline__ void rg_rows_fwd(const void* __restrict__ in, float2*
   fft_reg<L, false, kTwGlobal>(a, j, x, tw);
   if (ok) {
     const int rb = im.rb;
-    float2* dst = ws + im.ws_off + (int64_t)(u / rb) * L * rb + (u % rb);
+    float2* dst = ws + im.ws_off + (int64_t)(u / rb) * im.bs + (u % rb);
 #pragma unroll
     for (int q = 0; q < E; ++q) dst[(j + q * TPT) * rb] = cscale(a[q], scale);
   }
@@ -74,8 +75,8 @@ __device__ __forceinline__ void rg_cols(float2* __restrict__ ws, const RaggedIma
   const int v = t * w + ln.c;
   const bool ok = v < L;
   char* x = lds + ln.c * lds_region_bytes(L, w);
-  float2* base = ws + im.ws_off + (int64_t)ln.jh * L * rb + (ok ? v : 0) * rb + ln.s;
-  const int64_t qs = (int64_t)TPT * L;
+  float2* base = ws + im.ws_off + (int64_t)ln.jh * im.bs + (ok ? v : 0) * rb + ln.s;
+  const int64_t qs = (int64_t)(TPT / rb) * im.bs;
   float2 a[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) a[q] = ok ? base[q * qs] : make_float2(0.f, 0.f);
@@ -103,7 +104,7 @@ __device__ __forceinline__ void rg_rows_inv(const float2* __restrict__ ws, void*
   const bool ok = u < L;
   char* x = lds + r * lds_region_bytes(L, R);
   const int rb = im.rb;
-  const float2* src = ws + im.ws_off + (int64_t)((ok ? u : 0) / rb) * L * rb + ((ok ? u : 0) % rb);
+  const float2* src = ws + im.ws_off + (int64_t)((ok ? u : 0) / rb) * im.bs + ((ok ? u : 0) % rb);
   float2 a[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + (j + q * TPT) * rb) : make_float2(0.f, 0.f);
