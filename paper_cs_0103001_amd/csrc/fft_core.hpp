@@ -291,9 +291,9 @@ __device__ __forceinline__ void scatter_natural(const float2 (&a)[elems_per_thre
 }
 
 // Stage S-1 outputs -> LDS -> stage S inputs (natural positions j + q*TPT).
-template <int L, int S>
+template <int L, int S, bool SPLIT = kSplitExchange>
 __device__ __forceinline__ void exchange(float2 (&a)[elems_per_thread(L)], int j, void* x) {
-  if constexpr (kSplitExchange) {
+  if constexpr (SPLIT) {
     lds_barrier();  // earlier readers of x are done
     stage_store<L, S - 1, kRe>(a, j, x);
     lds_barrier();
@@ -392,37 +392,37 @@ __device__ __forceinline__ void load_twiddles_lds_mix(float2* twl, const float2*
   }
 }
 
-template <int L, int S, bool INV, int TWM>
+template <int L, int S, bool INV, int TWM, bool SPLIT = kSplitExchange>
 struct StageChain {
   __device__ __forceinline__ static void run(float2 (&a)[elems_per_thread(L)], int j, void* x,
                                              const float2* __restrict__ tws) {
     if constexpr (S < num_stages(L)) {
       if constexpr (TWM == kTwReg) {
-        exchange<L, S>(a, j, x);
+        exchange<L, S, SPLIT>(a, j, x);
         stage_compute<L, S, INV>(a, tws + reg_tw_offset<L>(S));
       } else if constexpr (TWM == kTwMix && !mix_in_lds(L, S)) {
-        exchange<L, S>(a, j, x);
+        exchange<L, S, SPLIT>(a, j, x);
         stage_compute<L, S, INV>(a, tws + reg_tw_offset_mix<L>(S));
       } else if constexpr (TWM == kTwMix) {
         // the small tables sit at the start of the workgroup's dynamic LDS
         extern __shared__ float4 lds_raw[];
         float2 tw[StageInfo<L, S>::NTW > 0 ? StageInfo<L, S>::NTW : 1];
-        exchange<L, S>(a, j, x);
+        exchange<L, S, SPLIT>(a, j, x);
         stage_twiddles_lds<L, S>(tw, j, reinterpret_cast<const float2*>(lds_raw));
         stage_compute<L, S, INV>(a, tw);
       } else {
         float2 tw[StageInfo<L, S>::NTW > 0 ? StageInfo<L, S>::NTW : 1];
         if constexpr (TWM == kTwLds) {
-          exchange<L, S>(a, j, x);
+          exchange<L, S, SPLIT>(a, j, x);
           stage_twiddles_lds<L, S>(tw, j, tws);
         } else {
           if constexpr (FFTMI_TW_PREFETCH) stage_twiddles<L, S>(tw, j, tws);
-          exchange<L, S>(a, j, x);
+          exchange<L, S, SPLIT>(a, j, x);
           if constexpr (!FFTMI_TW_PREFETCH) stage_twiddles<L, S>(tw, j, tws);
         }
         stage_compute<L, S, INV>(a, tw);
       }
-      StageChain<L, S + 1, INV, TWM>::run(a, j, x, tws);
+      StageChain<L, S + 1, INV, TWM, SPLIT>::run(a, j, x, tws);
     }
   }
 };
@@ -433,7 +433,7 @@ struct StageChain {
 // this the same number of times (it contains workgroup barriers when L > 16).
 // tws: the global tables (kTwGlobal), the LDS copy (kTwLds) or this thread's
 // register array from load_twiddles_reg (kTwReg).
-template <int L, bool INV, int TWM = kTwGlobal>
+template <int L, bool INV, int TWM = kTwGlobal, bool SPLIT = kSplitExchange>
 __device__ __forceinline__ void fft_reg(float2 (&a)[elems_per_thread(L)], int j, void* x,
                                         const float2* __restrict__ tws) {
   if constexpr (num_stages(L) > 0) {
@@ -446,7 +446,7 @@ __device__ __forceinline__ void fft_reg(float2 (&a)[elems_per_thread(L)], int j,
     if constexpr (TWM == kTwGlobal) asm volatile("" : "+s"(tw));
     asm volatile("" : "+v"(j));
     stage_compute<L, 0, INV>(a, nullptr);
-    StageChain<L, 1, INV, TWM>::run(a, j, x, tw);
+    StageChain<L, 1, INV, TWM, SPLIT>::run(a, j, x, tw);
   }
 }
 

@@ -88,9 +88,10 @@ constexpr int kLdsEntryBytes = kSplitExchange ? 4 : 8;
 #ifndef FFTMI_BANK_SPAN
 #define FFTMI_BANK_SPAN 128
 #endif
-FFTMI_HD constexpr int lds_region_bytes(int L, int inter) {
-  return kLdsEntryBytes *
-         (lds_size(L) + (inter > 1 && inter <= 32 ? (FFTMI_BANK_SPAN / kLdsEntryBytes) / inter : 0));
+// `split`: the kernel exchanges real and imaginary parts separately (4-byte
+// entries, half the LDS per transform).
+FFTMI_HD constexpr int lds_region_bytes(int L, int inter, bool split = kSplitExchange) {
+  return (split ? 4 : 8) * (lds_size(L) + (inter > 1 && inter <= 32 ? (FFTMI_BANK_SPAN / (split ? 4 : 8)) / inter : 0));
 }
 
 constexpr int kMaxLog2Row = 14;      // longest single-pass transform, 2^14

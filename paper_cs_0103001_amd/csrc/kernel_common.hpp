@@ -102,9 +102,44 @@ struct Twiddles<L, kTwMix> {
   __device__ __forceinline__ const float2* ptr() const { return r; }
 };
 
+// Transform configuration of one kernel: where its twiddle factors come from
+// and whether its LDS exchanges carry real and imaginary parts separately
+// (4-byte entries: half the LDS per transform, twice the barriers).  The
+// column pass and the row pass out of the blocked layout have their own.
+#ifndef FFTMI_TWM_COLS
+#define FFTMI_TWM_COLS FFTMI_TWM
+#endif
+#ifndef FFTMI_SPLIT_COLS
+#define FFTMI_SPLIT_COLS FFTMI_SPLIT_X
+#endif
+#ifndef FFTMI_TWM_ROWS_OUT
+#define FFTMI_TWM_ROWS_OUT FFTMI_TWM
+#endif
+#ifndef FFTMI_SPLIT_ROWS_OUT
+#define FFTMI_SPLIT_ROWS_OUT FFTMI_SPLIT_X
+#endif
+FFTMI_HD constexpr int twm_for(int L, int req) { return L <= (1 << kLdsTwMaxLog2) ? req : kTwGlobal; }
+FFTMI_HD constexpr int tw_lds_bytes_for(int L, int mode) {
+  return mode == kTwLds ? lds_tw_bytes(L) : (mode == kTwMix ? mix_lds_bytes(L) : 0);
+}
+template <int L, int TWM_REQ, bool SPLIT_REQ>
+struct XCfg {
+  static constexpr int TWM = twm_for(L, TWM_REQ);
+  static constexpr bool SPLIT = SPLIT_REQ;
+  static constexpr int TWB = tw_lds_bytes_for(L, TWM);
+  static constexpr int region(int inter) { return lds_region_bytes(L, inter, SPLIT); }
+};
 template <int L>
+using DefCfg = XCfg<L, FFTMI_TWM, kSplitExchange>;
+template <int L>
+using ColsCfg = XCfg<L, FFTMI_TWM_COLS, FFTMI_SPLIT_COLS != 0>;
+template <int L>
+using RowsOutCfg = XCfg<L, FFTMI_TWM_ROWS_OUT, FFTMI_SPLIT_ROWS_OUT != 0>;
+
+// The workgroup's transform regions follow its LDS twiddle tables.
+template <int L, class C = DefCfg<L>>
 __device__ __forceinline__ char* regions() {
-  return lds_base() + Shape<L>::TWB;
+  return lds_base() + C::TWB;
 }
 
 // Make a per-thread pointer opaque to the optimiser so that addresses derived

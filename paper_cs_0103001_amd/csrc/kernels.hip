@@ -11,6 +11,8 @@
 // stay in flight for the whole computation.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cstdlib>
 #include <map>
@@ -361,12 +363,13 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
                                                                 int rb, unsigned bs, int nt, int ntiles, float scale,
                                                                 const float2* __restrict__ tws) {
   using S = Shape<L>;
+  using C = RowsOutCfg<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const int lnt = ilog2_pow2(nt), lsub = ilog2_pow2(rb / nt);
   const int tid = threadIdx.x, sl = tid & (nt - 1), j = tid >> lnt;
-  const Twiddles<L> twd(tws, j);
+  const Twiddles<L, C::TWM> twd(tws, j);
   const float2* tw = twd.ptr();
-  char* x = regions<L>() + sl * lds_region_bytes(L, nt);
+  char* x = regions<L, C>() + sl * C::region(nt);
   const unsigned lane_in = (unsigned)(j * rb + sl), lane_out = (unsigned)(sl * L + j);
   const int qs = TPT * rb;
   float2 a[E], nx[Prefetch<L, kPassRowsOut>::on ? E : 1];
@@ -390,7 +393,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_from_blk(const float2* __
     } else {
       load(a, t);
     }
-    fft_reg<L, INV, S::TWM>(a, j, x, tw);
+    fft_reg<L, INV, C::TWM, C::SPLIT>(a, j, x, tw);
     const int64_t r0 = (int64_t)(t >> lsub) * rb + (t & ((1 << lsub) - 1)) * nt;
     if constexpr (F32) {
       float* b = static_cast<float*>(out) + r0 * L;
@@ -503,13 +506,14 @@ template <int L, int MK, bool HALF>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict__ ws, float2* __restrict__ save, int M,
                                                       int rb, unsigned bs, int w, int ltiles, int ntiles, MaskArgs mk,
                                                       const float2* __restrict__ tws) {
-  static_assert(!HALF || (!kSplitExchange && MK != FFT_MASK_TENSOR_F32), "half spectrum: analytic masks");
+  using C = std::conditional_t<HALF, DefCfg<L>, ColsCfg<L>>;
+  static_assert(!HALF || (!C::SPLIT && MK != FFT_MASK_TENSOR_F32), "half spectrum: analytic masks");
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
-  const Twiddles<L> twd(tws, ln.j);
+  const Twiddles<L, C::TWM> twd(tws, ln.j);
   const float2* tw = twd.ptr();
-  char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
+  char* x = regions<L, C>() + ln.c * C::region(w);
   // byte offsets: the thread's within a tile (VGPR), element q's and the
   // tile's within the image (SGPR)
   const unsigned qs8 = (unsigned)(TPT / rb) * bs * 8u;
@@ -538,7 +542,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
     const BlkBuf out(ws + (int64_t)(t >> ltiles) * img, (uint64_t)img * 8u);
     const unsigned toff = (unsigned)((t & tmask) * w * rb) * 8u;
     const int v = (t & tmask) * w + ln.c;
-    fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
+    fft_reg<L, false, C::TWM, C::SPLIT>(a, ln.j, x, tw);
     if (save) {
       const BlkBuf sb(save + (int64_t)(t >> ltiles) * img, (uint64_t)img * 8u);
 #pragma unroll
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
       const MaskEval<L, MK> me(mk, ln.j, v, mfreq);
       me.apply(a, ln.j, mk);
     }
-    fft_reg<L, true, S::TWM>(a, ln.j, x, tw);
+    fft_reg<L, true, C::TWM, C::SPLIT>(a, ln.j, x, tw);
 #pragma unroll
     for (int q = 0; q < E; ++q) out.st(a[q], vlane, toff + q * qs8);
     if constexpr (Prefetch<L, kPassCols>::on) {
@@ -971,9 +975,9 @@ constexpr int max_block() {
   return Shape<L>::LB;
 }
 
-template <int L>
+template <int L, class C = DefCfg<L>>
 const float2* twiddle_src(const Launch& lc) {
-  return Shape<L>::TWM == kTwLds ? lc.tw_lds : lc.tw;
+  return C::TWM == kTwLds ? lc.tw_lds : lc.tw;
 }
 
 #define FFTMI_LOG2_CASES(F) \
@@ -1018,7 +1022,7 @@ int pair_per_tile(int rb) {
 // threads), so that more of each block's interleaved segments are written by
 // one workgroup; the pass that reads it aims at 256-thread workgroups,
 // several of which share a CU.
-template <int L>
+template <int L, class C = DefCfg<L>>
 int rows_per_tile(int rb, int target) {
   int nt = rb;
   while (nt > 1 && nt * threads_per_transform(L) > target) nt /= 2;
@@ -1026,7 +1030,7 @@ int rows_per_tile(int rb, int target) {
     const int v = std::atoi(e);
     if (v >= 1 && v <= rb && (v & (v - 1)) == 0) nt = v;
   }
-  while (nt > 1 && (tw_bytes<L>() + nt * lds_region_bytes(L, nt) > kLdsBytes ||
+  while (nt > 1 && (C::TWB + nt * C::region(nt) > kLdsBytes ||
                     nt * threads_per_transform(L) > max_block<L>()))
     nt /= 2;
   return nt;
@@ -1075,9 +1079,10 @@ struct RowsFromBlk {
   static hipError_t run(bool inv, const float2* ws, void* out, bool out_f32, int64_t blocks, int rb, unsigned bs,
                         float scale, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
-    const float2* tw = twiddle_src<L>(lc);
-    const int nt = rows_per_tile<L>(rb, 256);
-    const int lds = tw_bytes<L>() + nt * lds_region_bytes(L, nt);
+    using C = RowsOutCfg<L>;
+    const float2* tw = twiddle_src<L, C>(lc);
+    const int nt = rows_per_tile<L, C>(rb, 256);
+    const int lds = C::TWB + nt * C::region(nt);
     const int64_t ntiles = blocks * (rb / nt);
     auto k = inv ? (out_f32 ? k_rows_from_blk<L, true, true> : k_rows_from_blk<L, true, false>)
                  : (out_f32 ? k_rows_from_blk<L, false, true> : k_rows_from_blk<L, false, false>);
@@ -1124,10 +1129,11 @@ struct ColsFilter {
   static hipError_t launch(float2* ws, float2* save, int64_t nimg, int M, int rb, unsigned bs, int w,
                            const MaskArgs& mk, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
+    using C = std::conditional_t<HALF, DefCfg<L>, ColsCfg<L>>;
     const int tiles = M / w;
-    const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
+    const int lds = C::TWB + w * C::region(w);
     const int64_t ntiles = nimg * tiles;
-    const float2* tw = twiddle_src<L>(lc);
+    const float2* tw = twiddle_src<L, C>(lc);
     const int lt = ilog2c(tiles);
     switch (mk.kind) {
       case FFT_MASK_TENSOR_F32:
@@ -1404,7 +1410,11 @@ hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, cons
 
 static int tw_lds_bytes_rt(int L) { return L <= (1 << kLdsTwMaxLog2) ? lds_tw_bytes(L) : 0; }
 int lds_bytes_rows_rm(int log2L, int tpw) { return tw_lds_bytes_rt(1 << log2L) + tpw * lds_region_bytes(1 << log2L, 1); }
-int lds_bytes_cols(int log2L, int w) { return tw_lds_bytes_rt(1 << log2L) + w * lds_region_bytes(1 << log2L, w); }
+int lds_bytes_cols(int log2L, int w) {
+  const int L = 1 << log2L;
+  const int cols = tw_lds_bytes_for(L, twm_for(L, FFTMI_TWM_COLS)) + w * lds_region_bytes(L, w, FFTMI_SPLIT_COLS != 0);
+  return std::max(cols, tw_lds_bytes_rt(L) + w * lds_region_bytes(L, w));
+}
 int max_block_threads(int log2L) { return threads_per_transform(1 << log2L) > 512 ? 1024 : 512; }
 int lds_bytes_rows_blk(int log2L, int nt) {
   return tw_lds_bytes_rt(1 << log2L) + nt * lds_region_bytes(1 << log2L, nt);

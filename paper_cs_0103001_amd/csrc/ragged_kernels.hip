@@ -7,7 +7,11 @@
 // that length, so a single launch covers every size.  A tile is always
 // T/TPT(s) transforms of 16 points per thread (T*16 points), whatever the
 // image side s, which makes tiles of different images cost about the same.
-// Twiddles come from the global FP32 tables of each length (one per side).
+// Twiddles (the FP32 tables of each side, rounded once from FP64): the short
+// stage tables (stride <= 16) are copied into the front of LDS whenever a
+// workgroup moves to a tile of another side (tiles are sorted by side), the
+// long-stride stages' factors are loaded into registers at the start of each
+// tile, next to the tile's data.
 //
 // Image i of side s occupies elements [off, off + s*s) of the packed input
 // and output (row-major) and (s / rb) * bs elements from ws_off in the
@@ -31,6 +35,22 @@ namespace fftmi {
 namespace {
 
 constexpr int kRaggedMaxBlock = 512;
+// LDS bytes reserved for the short stage tables (the largest, 2048 points:
+// 15 x 16 entries)
+constexpr int kRgTwBytes = 2048;
+static_assert(mix_lds_bytes(1 << kRaggedMaxLog2) <= kRgTwBytes, "ragged twiddle area");
+
+// Short stage tables of side 2^lg into the front of LDS when the workgroup's
+// current side changes (a uniform branch).  The barrier keeps the copy from
+// overwriting factors the previous tile may still read; the transform's first
+// exchange orders the copy before the new tile's reads.
+template <int L>
+__device__ __forceinline__ void rg_tw_lds(const float2* __restrict__ tw) {
+  if constexpr (mix_lds_entries(L) > 0) {
+    extern __shared__ float4 lds_raw[];
+    load_twiddles_lds_mix<L>(reinterpret_cast<float2*>(lds_raw), tw, threadIdx.x, blockDim.x);
+  }
+}
 
 // Forward row transforms of one tile: rows u = t*R + r of the image, f32 or
 // c64 input, scaled, stored into the blocked workspace.
@@ -54,7 +74,9 @@ __device__ __forceinline__ void rg_rows_fwd(const void* __restrict__ in, float2*
 #pragma unroll
     for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + j + q * TPT) : make_float2(0.f, 0.f);
   }
-  fft_reg<L, false, kTwGlobal>(a, j, x, tw);
+  float2 twr[reg_tw_count_mix<L>()];
+  load_twiddles_reg_mix<L>(twr, j, tw);
+  fft_reg<L, false, kTwMix>(a, j, x, twr);
   if (ok) {
     const int rb = im.rb;
     float2* dst = ws + im.ws_off + (int64_t)(u / rb) * im.bs + (u % rb);
@@ -80,12 +102,14 @@ __device__ __forceinline__ void rg_cols(float2* __restrict__ ws, const RaggedIma
   float2 a[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) a[q] = ok ? base[q * qs] : make_float2(0.f, 0.f);
-  fft_reg<L, false, kTwGlobal>(a, ln.j, x, tw);
+  float2 twr[reg_tw_count_mix<L>()];
+  load_twiddles_reg_mix<L>(twr, ln.j, tw);
+  fft_reg<L, false, kTwMix>(a, ln.j, x, twr);
   MaskArgs mk = mk0;
   mk.inv_n = mk.inv_m = 1.0f / (float)L;
   const MaskEval<L, MK> me(mk, ln.j, v, L);
   me.apply(a, ln.j, mk);
-  fft_reg<L, true, kTwGlobal>(a, ln.j, x, tw);
+  fft_reg<L, true, kTwMix>(a, ln.j, x, twr);
   if (ok) {
 #pragma unroll
     for (int q = 0; q < E; ++q) base[q * qs] = a[q];
@@ -108,7 +132,9 @@ __device__ __forceinline__ void rg_rows_inv(const float2* __restrict__ ws, void*
   float2 a[E];
 #pragma unroll
   for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + (j + q * TPT) * rb) : make_float2(0.f, 0.f);
-  fft_reg<L, true, kTwGlobal>(a, j, x, tw);
+  float2 twr[reg_tw_count_mix<L>()];
+  load_twiddles_reg_mix<L>(twr, j, tw);
+  fft_reg<L, true, kTwMix>(a, j, x, twr);
   if (ok) {
     if constexpr (OUT_F32) {
       float* dst = static_cast<float*>(out) + im.off + (int64_t)u * L;
@@ -132,11 +158,12 @@ __device__ __forceinline__ float rg_scale(int lg, int fwd, int numpy) {
 #define FFTMI_RG_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11)
 
 template <bool IN_F32>
-__global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_rows_fwd(const void* __restrict__ in, float2* __restrict__ ws,
+__global__ __launch_bounds__(kRaggedMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_ragged_rows_fwd(const void* __restrict__ in, float2* __restrict__ ws,
                                                                      const RaggedImage* __restrict__ imgs,
                                                                      const int2* __restrict__ tiles, int ntiles,
                                                                      TwTable tw, int numpy) {
-  char* lds = lds_base();
+  char* lds = lds_base() + kRgTwBytes;
+  int cur_lg = -1;
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int2 tl = tiles[tile_of(n, ntiles)];
     const RaggedImage im = imgs[tl.x];
@@ -144,6 +171,11 @@ __global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_rows_fwd(const void*
     switch (im.lg) {
 #define FFTMI_RG_ROWS_FWD(K)                                              \
   case K:                                                                 \
+    if (im.lg != cur_lg) {                                                \
+      lds_barrier();                                                      \
+      rg_tw_lds<1 << K>(tw.p[K]);                                         \
+      cur_lg = im.lg;                                                     \
+    }                                                                     \
     rg_rows_fwd<1 << K, IN_F32>(in, ws, im, tl.y, tw.p[K], lds, sc);      \
     break;
       FFTMI_RG_CASES(FFTMI_RG_ROWS_FWD)
@@ -155,17 +187,23 @@ __global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_rows_fwd(const void*
 }
 
 template <int MK>
-__global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_cols(float2* __restrict__ ws,
+__global__ __launch_bounds__(kRaggedMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_ragged_cols(float2* __restrict__ ws,
                                                                  const RaggedImage* __restrict__ imgs,
                                                                  const int2* __restrict__ tiles, int ntiles,
                                                                  MaskArgs mk, TwTable tw) {
-  char* lds = lds_base();
+  char* lds = lds_base() + kRgTwBytes;
+  int cur_lg = -1;
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int2 tl = tiles[tile_of(n, ntiles)];
     const RaggedImage im = imgs[tl.x];
     switch (im.lg) {
 #define FFTMI_RG_COLS(K)                                  \
   case K:                                                 \
+    if (im.lg != cur_lg) {                                                \
+      lds_barrier();                                                      \
+      rg_tw_lds<1 << K>(tw.p[K]);                                         \
+      cur_lg = im.lg;                                                     \
+    }                                                                     \
     rg_cols<1 << K, MK>(ws, im, tl.y, mk, tw.p[K], lds);  \
     break;
       FFTMI_RG_CASES(FFTMI_RG_COLS)
@@ -177,11 +215,12 @@ __global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_cols(float2* __restr
 }
 
 template <bool OUT_F32>
-__global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_rows_inv(const float2* __restrict__ ws, void* __restrict__ out,
+__global__ __launch_bounds__(kRaggedMaxBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_ragged_rows_inv(const float2* __restrict__ ws, void* __restrict__ out,
                                                                      const RaggedImage* __restrict__ imgs,
                                                                      const int2* __restrict__ tiles, int ntiles,
                                                                      TwTable tw, int numpy) {
-  char* lds = lds_base();
+  char* lds = lds_base() + kRgTwBytes;
+  int cur_lg = -1;
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int2 tl = tiles[tile_of(n, ntiles)];
     const RaggedImage im = imgs[tl.x];
@@ -189,6 +228,11 @@ __global__ __launch_bounds__(kRaggedMaxBlock) void k_ragged_rows_inv(const float
     switch (im.lg) {
 #define FFTMI_RG_ROWS_INV(K)                                              \
   case K:                                                                 \
+    if (im.lg != cur_lg) {                                                \
+      lds_barrier();                                                      \
+      rg_tw_lds<1 << K>(tw.p[K]);                                         \
+      cur_lg = im.lg;                                                     \
+    }                                                                     \
     rg_rows_inv<1 << K, OUT_F32>(ws, out, im, tl.y, tw.p[K], lds, sc);    \
     break;
       FFTMI_RG_CASES(FFTMI_RG_ROWS_INV)
@@ -236,13 +280,13 @@ hipError_t rg_grid(const void* fn, int block, int lds, int cap, int ntiles, int*
 }  // namespace
 
 int ragged_lds_bytes(int block) {
-  int most = 0;
+  int most = 0;  // transform regions, after the twiddle area
   for (int lg = 0; lg <= kRaggedMaxLog2; ++lg) {
     const int L = 1 << lg, tpt = threads_per_transform(L);
     const int per = block / tpt;  // transforms per tile
     most = std::max(most, per * lds_region_bytes(L, per));
   }
-  return most;
+  return kRgTwBytes + most;
 }
 
 namespace {
