@@ -39,7 +39,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and B._lib is not None:
+        if h is not None and B is not None and getattr(B, "_lib", None) is not None:
             try:
                 B.fft_plan_destroy(h)
             except Exception:
