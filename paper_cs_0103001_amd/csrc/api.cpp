@@ -335,9 +335,12 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       p->ws_bytes = p->part_off + (size_t)p->grad_groups * (size_t)N * (size_t)M * sizeof(float);
     }
     // then the fused MSE forward's per-tile loss sums (at most one per row)
+    // and the doubles of their two-level sum
     if (!p->half) {
       p->loss_off = (p->ws_bytes + 255) & ~(size_t)255;
-      p->ws_bytes = p->loss_off + (size_t)std::max<int64_t>(batch * N, 1) * sizeof(float);
+      const int64_t nparts = std::max<int64_t>(batch * N, 1);
+      p->loss_mid_off = (p->loss_off + (size_t)nparts * sizeof(float) + 255) & ~(size_t)255;
+      p->ws_bytes = p->loss_mid_off + (size_t)sum_partials_scratch(nparts) * sizeof(double);
     }
   }
   plan_register(p.get());
@@ -670,7 +673,8 @@ int fft2d_filter_mse(fft_plan_t p, const float* x, const float* c, const float* 
     if (e != hipSuccess) return hip_fail(e);
     nparts += nt;
   }
-  hipError_t e = launch_sum_partials(part, nparts, weight, loss, st);
+  double* mid = reinterpret_cast<double*>(static_cast<char*>(workspace) + p->loss_mid_off);
+  hipError_t e = launch_sum_partials(part, nparts, weight, loss, mid, st);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 

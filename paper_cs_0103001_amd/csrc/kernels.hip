@@ -472,13 +472,33 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_loss(const float2* __rest
   }
 }
 
-// out[0] = weight * (part[0] + ... + part[n-1]), in double precision, in a
-// fixed order (one workgroup of 256 threads).
-__global__ __launch_bounds__(256) void k_sum_partials(const float* __restrict__ part, int64_t n, float weight,
-                                                      float* __restrict__ out) {
+// out[0] = weight * (part[0] + ... + part[n-1]) in double precision, in a
+// fixed order, in two launches: workgroup g of the first adds its run of
+// kSumRun consecutive partials (thread t takes elements t, t + 256, ... of
+// the run, then a fixed tree in LDS) into mid[g]; one workgroup then adds
+// mid[0 .. G) the same way.  The order depends only on n.
+constexpr int kSumRun = 4096;
+__global__ __launch_bounds__(256) void k_sum_runs(const float* __restrict__ part, int64_t n,
+                                                  double* __restrict__ mid) {
+  __shared__ double red[256];
+  const int64_t i0 = (int64_t)blockIdx.x * kSumRun;
+  const int64_t i1 = min(n, i0 + kSumRun);
+  double s = 0.0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += (double)part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mid[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_mid(const double* __restrict__ mid, int g, float weight,
+                                                 float* __restrict__ out) {
   __shared__ double red[256];
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)part[i];
+  for (int i = threadIdx.x; i < g; i += 256) s += mid[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -711,7 +731,7 @@ __global__ __launch_bounds__(256) void k_unblock_mag(const float2* __restrict__ 
 // Mask gradient.  A tile is (image group g, column tile): loop over the
 // group's images in order, forward-transform the blocked rows of the incoming
 // gradient (or residual), multiply by conj(saved spectrum X) and accumulate
-// the real part, prefetching the next image's tile meanwhile.  The group's
+// the real part.  The group's
 // partial sum goes to part[g][u][v]:
 //   w_lin * sum_b Re(conj X_b . T_b)  (+ w_sq * (m - 1) * sum_b |X_b|^2  when MT)
 // where T_b is the unscaled transform.  Partials of consecutive groups are
@@ -743,23 +763,20 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
     float acc[E], acc2[E];
 #pragma unroll
     for (int q = 0; q < E; ++q) acc[q] = acc2[q] = 0.f;
-    float2 a[E], nx[E];
-    {
-      const float2* b = ws + b0 * plane + ct * w * rb;
-      const unsigned f_lane = fresh(lane);
-#pragma unroll
-      for (int q = 0; q < E; ++q) a[q] = ld(b, f_lane + q * qs);
-    }
-    settle(a);
+    // one image at a time: the residual's loads, its transform, then the
+    // saved spectrum's loads and the products.  No next-image prefetch: the
+    // spectrum loads would wait behind it (loads complete in order), and
+    // without it the kernel fits four workgroups per CU.
     for (int bi = b0; bi < b1; ++bi) {
-      if (bi + 1 < b1) {
-        const float2* b = ws + (bi + 1) * plane + ct * w * rb;
+      float2 a[E];
+      const float2* b = ws + bi * plane + ct * w * rb;
+      const float2* xs = save + bi * plane + ct * w * rb;
+      {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) nx[q] = ld(b, f_lane + q * qs);
+        for (int q = 0; q < E; ++q) a[q] = ld(b, f_lane + q * qs);
       }
       fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
-      const float2* xs = save + bi * plane + ct * w * rb;
       {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
@@ -769,8 +786,6 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
           if constexpr (MT) acc2[q] = fmaf(X.x, X.x, fmaf(X.y, X.y, acc2[q]));
         }
       }
-#pragma unroll
-      for (int q = 0; q < E; ++q) a[q] = nx[q];
     }
     const unsigned f_lane_out = fresh(lane_out);
     float* dst = part + (int64_t)g * L * M + ct * w;
@@ -1279,8 +1294,12 @@ hipError_t launch_rows_loss(int log2L, const float2* ws, const float* x, const f
   FFTMI_DISPATCH(RowsLoss, log2L)
 }
 
-hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, part, n, weight, out);
+int64_t sum_partials_scratch(int64_t n) { return std::max<int64_t>(1, (n + kSumRun - 1) / kSumRun); }
+
+hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float* out, double* mid, hipStream_t st) {
+  const int64_t g = sum_partials_scratch(n);
+  if (n > 0) hipLaunchKernelGGL(k_sum_runs, dim3((unsigned)g), dim3(256), 0, st, part, n, mid);
+  hipLaunchKernelGGL(k_sum_mid, dim3(1), dim3(256), 0, st, mid, n > 0 ? (int)g : 0, weight, out);
   return hipGetLastError();
 }
 

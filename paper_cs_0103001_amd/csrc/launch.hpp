@@ -54,8 +54,10 @@ hipError_t launch_rows_to_blk_diff(int log2L, const float* in, const float* in2,
 hipError_t launch_rows_loss(int log2L, const float2* ws, const float* x, const float* c, float* part, int64_t blocks,
                             int rb, unsigned bs, float scale, int64_t* ntiles, const Launch& lc);
 
-// out[0] = weight * sum of part[0 .. n), double precision, fixed order.
-hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float* out, hipStream_t st);
+// out[0] = weight * sum of part[0 .. n), double precision, fixed order; mid
+// holds sum_partials_scratch(n) doubles of intermediate sums.
+int64_t sum_partials_scratch(int64_t n);
+hipError_t launch_sum_partials(const float* part, int64_t n, float weight, float* out, double* mid, hipStream_t st);
 
 // Half-spectrum path for real rows (pass one): rows in pairs, columns
 // 0 .. L/2-1 of each row's spectrum into blocks of L/2 columns, column 0

@@ -57,7 +57,7 @@ struct fftmi_plan {
   // rank 2: image groups of the mask-gradient column pass, and the workspace
   // offsets of their partial sums and of the fused MSE forward's per-tile sums
   int grad_groups = 1;
-  size_t part_off = 0, loss_off = 0;
+  size_t part_off = 0, loss_off = 0, loss_mid_off = 0;
   fftmi::RaggedState* ragged = nullptr;
 };
 
