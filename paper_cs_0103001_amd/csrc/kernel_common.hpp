@@ -40,13 +40,29 @@ __device__ __forceinline__ char* lds_base() {
 #ifndef FFTMI_PF_ROWS_OUT
 #define FFTMI_PF_ROWS_OUT 0
 #endif
-enum { kPassRowsIn = 0, kPassCols = 1, kPassRowsOut = 2 };
+#ifndef FFTMI_PF_ROWS_1D
+#define FFTMI_PF_ROWS_1D 0
+#endif
+enum { kPassRowsIn = 0, kPassCols = 1, kPassRowsOut = 2, kPassRows1D = 3 };
+// Transforms of 2^14 points take 1024-thread workgroups, whose threads have
+// at most 128 VGPRs: too few for a second tile, so they never prefetch.
 template <int L, int PASS>
 struct Prefetch {
-  static constexpr bool on = L > 0 && (PASS == kPassRowsIn ? FFTMI_PF_ROWS_IN != 0
+  static constexpr bool on = L > 0 && threads_per_transform(L) <= 512 && (PASS == kPassRowsIn ? FFTMI_PF_ROWS_IN != 0
                                        : PASS == kPassCols ? FFTMI_PF_COLS != 0
-                                                           : FFTMI_PF_ROWS_OUT != 0);
+                                       : PASS == kPassRowsOut ? FFTMI_PF_ROWS_OUT != 0
+                                                              : FFTMI_PF_ROWS_1D != 0);
 };
+
+// Mixed twiddles need little LDS at any length; the register share grows
+// with the stages beyond the first, so they are used up to 2^FFTMI_MIX_MAX_LOG2.
+#ifndef FFTMI_MIX_MAX_LOG2
+#define FFTMI_MIX_MAX_LOG2 12
+#endif
+FFTMI_HD constexpr int twm_for(int L, int req, int mix_max_log2 = FFTMI_MIX_MAX_LOG2) {
+  return req == kTwMix ? (L <= (1 << mix_max_log2) ? kTwMix : kTwGlobal)
+                       : (L <= (1 << kLdsTwMaxLog2) ? req : kTwGlobal);
+}
 
 template <int L>
 struct Shape {
@@ -58,7 +74,7 @@ struct Shape {
   static constexpr int LB = TPT > 512 ? 1024 : 512;
   // Twiddles: in registers up to 2^12 points (30 complex values per thread),
   // from the global tables beyond.
-  static constexpr int TWM = L <= (1 << kLdsTwMaxLog2) ? FFTMI_TWM : kTwGlobal;
+  static constexpr int TWM = twm_for(L, FFTMI_TWM);
   static constexpr int TWB = TWM == kTwLds ? lds_tw_bytes(L) : (TWM == kTwMix ? mix_lds_bytes(L) : 0);  // LDS bytes
 };
 
@@ -118,13 +134,12 @@ struct Twiddles<L, kTwMix> {
 #ifndef FFTMI_SPLIT_ROWS_OUT
 #define FFTMI_SPLIT_ROWS_OUT FFTMI_SPLIT_X
 #endif
-FFTMI_HD constexpr int twm_for(int L, int req) { return L <= (1 << kLdsTwMaxLog2) ? req : kTwGlobal; }
 FFTMI_HD constexpr int tw_lds_bytes_for(int L, int mode) {
   return mode == kTwLds ? lds_tw_bytes(L) : (mode == kTwMix ? mix_lds_bytes(L) : 0);
 }
-template <int L, int TWM_REQ, bool SPLIT_REQ>
+template <int L, int TWM_REQ, bool SPLIT_REQ, int MIX_MAX_LOG2 = FFTMI_MIX_MAX_LOG2>
 struct XCfg {
-  static constexpr int TWM = twm_for(L, TWM_REQ);
+  static constexpr int TWM = twm_for(L, TWM_REQ, MIX_MAX_LOG2);
   static constexpr bool SPLIT = SPLIT_REQ;
   static constexpr int TWB = tw_lds_bytes_for(L, TWM);
   static constexpr int region(int inter) { return lds_region_bytes(L, inter, SPLIT); }
@@ -135,6 +150,11 @@ template <int L>
 using ColsCfg = XCfg<L, FFTMI_TWM_COLS, FFTMI_SPLIT_COLS != 0>;
 template <int L>
 using RowsOutCfg = XCfg<L, FFTMI_TWM_ROWS_OUT, FFTMI_SPLIT_ROWS_OUT != 0>;
+// 1D transforms in one pass (up to 2^14 points): mixed twiddles at every
+// length, since these kernels run without a prefetch buffer (2^13 points:
+// 4.1 TB/s against 3.1 with the global tables and a prefetch).
+template <int L>
+using Rows1DCfg = XCfg<L, FFTMI_TWM, kSplitExchange, kMaxLog2Row>;
 
 // The workgroup's transform regions follow its LDS twiddle tables.
 template <int L, class C = DefCfg<L>>

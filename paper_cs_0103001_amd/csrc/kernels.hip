@@ -38,13 +38,14 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
                                                   int out_f32, int64_t rows, int tpw, int ntiles, float scale,
                                                   const float2* __restrict__ tws) {
   using S = Shape<L>;
+  using C = Rows1DCfg<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const int tid = threadIdx.x, t = tid / TPT, j = tid - t * TPT;
-  const Twiddles<L> twd(tws, j);
+  const Twiddles<L, C::TWM> twd(tws, j);
   const float2* tw = twd.ptr();
-  char* x = regions<L>() + t * lds_region_bytes(L, 1);
+  char* x = regions<L, C>() + t * C::region(1);
   const unsigned lane = (unsigned)(t * L + j);
-  float2 a[E], nx[E];
+  float2 a[E], nx[Prefetch<L, kPassRows1D>::on ? E : 1];
   auto load = [&](float2(&d)[E], int tile) __attribute__((always_inline)) {
     const bool ok = (int64_t)tile * tpw + t < rows;
     if (in_f32) {
@@ -64,12 +65,18 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
     }
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
-  settle(a);
+  if constexpr (Prefetch<L, kPassRows1D>::on) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+    settle(a);
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int tile = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
-    fft_reg<L, INV, S::TWM>(a, j, x, tw);
+    if constexpr (Prefetch<L, kPassRows1D>::on) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, tile);
+    }
+    fft_reg<L, INV, C::TWM, C::SPLIT>(a, j, x, tw);
     if ((int64_t)tile * tpw + t < rows) {
       if (out_f32) {
         float* b = static_cast<float*>(out) + (int64_t)tile * tpw * L;
@@ -87,8 +94,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
         }
       }
     }
+    if constexpr (Prefetch<L, kPassRows1D>::on) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = nx[q];
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
   }
 }
 
@@ -232,7 +241,8 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __
   const float2* tw = twd.ptr();
   float2* x = reinterpret_cast<float2*>(reg + p * RBY);
   const unsigned lane = (unsigned)(j * np);
-  float4 a[EH], nx[EH];
+  constexpr bool PF = TPT <= 512;  // 1024-thread transforms have no room for a second tile
+  float4 a[EH], nx[PF ? EH : 1];
   auto pair_of = [&](int t) __attribute__((always_inline)) { return (t & ((1 << lsub) - 1)) * npt + p; };
   auto load = [&](float4(&d)[EH], int t) __attribute__((always_inline)) {
     const float4* b = reinterpret_cast<const float4*>(ws + (int64_t)(t >> lsub) * bs) + pair_of(t);
@@ -241,12 +251,18 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __
     for (int q = 0; q < EH; ++q) d[q] = ld(b, l + q * TPT * np);
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+  if constexpr (PF) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
 #pragma unroll
-  for (int q = 0; q < EH; ++q) asm volatile("" : "+v"(a[q].x), "+v"(a[q].y), "+v"(a[q].z), "+v"(a[q].w));
+    for (int q = 0; q < EH; ++q) asm volatile("" : "+v"(a[q].x), "+v"(a[q].y), "+v"(a[q].z), "+v"(a[q].w));
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    if constexpr (PF) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, t);
+    }
     lds_barrier();  // the previous tile's readers of x are done
 #pragma unroll
     for (int q = 0; q < EH; ++q) {
@@ -287,8 +303,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_c2r_pair(const float2* __
         st_nt(&o[l + L + q * TPT], make_float2(w[q].y * scale, 0.f));
       }
     }
+    if constexpr (PF) {
 #pragma unroll
-    for (int q = 0; q < EH; ++q) a[q] = nx[q];
+      for (int q = 0; q < EH; ++q) a[q] = nx[q];
+    }
   }
 }
 
@@ -840,7 +858,8 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
   const unsigned qs = (unsigned)(TPT * C);
   const unsigned lane = (unsigned)(j * C + c);
   const int tmask = (1 << ltiles) - 1;
-  float2 a[E], nx[E];
+  constexpr bool PF = TPT <= 512;  // 1024-thread transforms have no room for a second tile
+  float2 a[E], nx[PF ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
     const float2* b = in + (int64_t)(t >> ltiles) * N + (t & tmask) * w;
     {
@@ -850,11 +869,17 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
     }
   };
   int n = blockIdx.x;
-  if (n < ntiles) load(a, (int)tile_of(n, ntiles));
-  settle(a);
+  if constexpr (PF) {
+    if (n < ntiles) load(a, (int)tile_of(n, ntiles));
+    settle(a);
+  }
   for (; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    if constexpr (PF) {
+      if (n + (int)gridDim.x < ntiles) load(nx, (int)tile_of(n + gridDim.x, ntiles));
+    } else {
+      load(a, t);
+    }
     const int64_t bo = (int64_t)(t >> ltiles) * N;
     const int c0 = (t & tmask) * w;
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
@@ -910,8 +935,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
         for (int q = 0; q < E; ++q) b[f_lane + q * qs] = cscale(a[q], scale);
       }
     }
+    if constexpr (PF) {
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = nx[q];
+      for (int q = 0; q < E; ++q) a[q] = nx[q];
+    }
   }
 }
 
@@ -1006,9 +1033,10 @@ struct RowsRm {
     int tpw = TPT >= 256 ? 1 : 256 / TPT;
     static_assert(TPT <= max_block<L>(), "block");
     if (rows < tpw) tpw = (int)(rows > 0 ? rows : 1);
-    const int lds = tw_bytes<L>() + tpw * lds_region_bytes(L, 1);
+    using C = Rows1DCfg<L>;
+    const int lds = C::TWB + tpw * C::region(1);
     const int ntiles = (int)((rows + tpw - 1) / tpw);
-    const float2* tw = twiddle_src<L>(lc);
+    const float2* tw = twiddle_src<L, C>(lc);
     if (inv)
       return go(k_rows_rm<L, true>, ntiles, tpw * TPT, lds, lc.stream, in, (int)in_f32, out, (int)out_f32, rows, tpw,
                 ntiles, scale, tw);
