@@ -20,7 +20,7 @@ def _api():
 
 
 SHAPES = [(1, 1), (2, 2), (1, 16), (16, 1), (4, 8), (16, 16), (32, 64), (64, 32), (256, 256), (128, 1024),
-          (1024, 128), (64, 4096), (4096, 64), (8192, 16), (16, 8192)]
+          (1024, 128), (64, 4096), (4096, 64), (8192, 16), (16, 8192), (16384, 16), (16, 16384)]
 
 
 @pytest.mark.parametrize("N,M", SHAPES)
@@ -60,7 +60,8 @@ def test_small_256_gaussian_workload():
 
 @pytest.mark.parametrize("N,M,kind", [(512, 512, "butterworth"), (64, 256, "butterworth"), (256, 64, "gaussian"),
                                       (512, 512, "disc"), (32, 32, "tensor"), (1024, 1024, "tensor"),
-                                      (16, 16, "gaussian"), (4, 8, "butterworth"), (1, 1, "gaussian")])
+                                      (16, 16, "gaussian"), (4, 8, "butterworth"), (1, 1, "gaussian"),
+                                      (32, 16384, "butterworth"), (16384, 32, "gaussian")])
 @pytest.mark.parametrize("complex_in", [False, True])
 def test_filter_kinds_vs_oracle(N, M, kind, complex_in):
     api = _api()
