@@ -241,6 +241,14 @@ int64_t fftmi::block_pad(int64_t stride) {
   return (stride * (int64_t)sizeof(float2)) % 4096 == 0 ? 32 : 0;
 }
 
+int fftmi::fourstep_pad(int log_n1) {
+  if (const char* e = std::getenv("FFTMI_FS_PAD")) {
+    const int v = std::atoi(e);
+    if (v >= 0 && v <= 4096 && v % 32 == 0) return v;
+  }
+  return (int)block_pad(int64_t(1) << log_n1);
+}
+
 extern "C" {
 
 int fft_version(void) { return 0x000100; }
@@ -302,11 +310,19 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       p->fourstep = true;
       p->log_n1 = p->log_n / 2;
       p->log_n2 = p->log_n - p->log_n1;
-      p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, 16);
-      p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, 16);
+      int wmax = 16;
+      if (const char* e = std::getenv("FFTMI_FS_W")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 16 && (v & (v - 1)) == 0) wmax = v;
+      }
+      p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, wmax);
+      p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, wmax);
       rc = fourstep_tables(t, p->log_n, &p->tw_lo, &p->tw_hi, &p->tw_h);
       if (rc != FFT_OK) return rc;
-      p->ws_bytes = (size_t)batch * (size_t)N * sizeof(float2);
+      // the intermediate [N2][N1] rows get a padded stride, so that the
+      // second pass's column reads do not all land on the same channels
+      p->fs_rs = (1 << p->log_n1) + fourstep_pad(p->log_n1);
+      p->ws_bytes = (size_t)batch * (size_t)(1 << p->log_n2) * (size_t)p->fs_rs * sizeof(float2);
     }
   } else {
     // rows per block of the blocked layout: limited by the column pass's
@@ -453,13 +469,14 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
     // the [N2][N1] intermediate, natural-order result.
     const int n1 = 1 << p->log_n1, n2 = 1 << p->log_n2;
     float2* ws = static_cast<float2*>(workspace);
+    const int64_t wsb = (int64_t)n2 * p->fs_rs;
     Launch l1 = launch_for(st, p->tables, p->log_n1);
     e = launch_cols_strided(p->log_n1, inv_tw, true, static_cast<const float2*>(in), ws, p->batch, n2, p->w1, 1.0f,
-                            p->tw_lo, p->tw_hi, p->tw_h, l1);
+                            p->tw_lo, p->tw_hi, p->tw_h, p->n, n2, wsb, p->fs_rs, l1);
     if (e != hipSuccess) return hip_fail(e);
     Launch l2 = launch_for(st, p->tables, p->log_n2);
     e = launch_cols_strided(p->log_n2, inv_tw, false, ws, static_cast<float2*>(out), p->batch, n1, p->w2, scale,
-                            nullptr, nullptr, 0, l2);
+                            nullptr, nullptr, 0, wsb, p->fs_rs, p->n, n1, l2);
     return e == hipSuccess ? FFT_OK : hip_fail(e);
   }
 

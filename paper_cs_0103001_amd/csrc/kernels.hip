@@ -836,15 +836,18 @@ __global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ p
 }
 
 // ============================================================== kernel E
-// Strided column pass over a row-major [L][C] matrix per batch entry (the
-// four-step long 1D transform).  twiddle_transpose: pass one (multiply by
-// W_N^{k1 n2} from two-level tables and store transposed as [C][L]).
+// Strided column pass over an [L][C] matrix per batch entry (the four-step
+// long 1D transform): row r of entry b starts at b*ib + r*irs.
+// twiddle_transpose: pass one (multiply by W_N^{k1 n2} from two-level tables
+// and store transposed, column c as the row of L entries at b*ob + c*ors);
+// otherwise pass two (store [L][C] with row stride ors).
 template <int L, bool INV>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __restrict__ in, float2* __restrict__ out,
                                                        int C, int w, int ltiles, int ntiles, int twiddle_transpose,
                                                        float scale, const float2* __restrict__ tlo,
                                                        const float2* __restrict__ thi, int h,
-                                                       const float2* __restrict__ tws) {
+                                                       const float2* __restrict__ tws, int64_t ib, int irs,
+                                                       int64_t ob, int ors) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const int lw = ilog2_pow2(w);
@@ -854,14 +857,13 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
   const int rbytes = lds_region_bytes(L, w);
   char* reg = regions<L>();
   char* x = reg + c * rbytes;
-  const int64_t N = (int64_t)L * C;
-  const unsigned qs = (unsigned)(TPT * C);
-  const unsigned lane = (unsigned)(j * C + c);
+  const unsigned qs = (unsigned)(TPT * irs);
+  const unsigned lane = (unsigned)(j * irs + c);
   const int tmask = (1 << ltiles) - 1;
   constexpr bool PF = TPT <= 512;  // 1024-thread transforms have no room for a second tile
   float2 a[E], nx[PF ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
-    const float2* b = in + (int64_t)(t >> ltiles) * N + (t & tmask) * w;
+    const float2* b = in + (int64_t)(t >> ltiles) * ib + (t & tmask) * w;
     {
       const unsigned f_lane = fresh(lane);
 #pragma unroll
@@ -880,7 +882,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
     } else {
       load(a, t);
     }
-    const int64_t bo = (int64_t)(t >> ltiles) * N;
+    const int64_t bo = (int64_t)(t >> ltiles) * ob;
     const int c0 = (t & tmask) * w;
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
     if (twiddle_transpose) {
@@ -924,15 +926,19 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
           o[e] = reinterpret_cast<const float2*>(reg + cc * rbytes)[lds_pad(k)];
         }
       }
-      float2* b = out + bo + (int64_t)c0 * L;
+      float2* b = out + bo + (int64_t)c0 * ors;
 #pragma unroll
-      for (int e = 0; e < E; ++e) b[(unsigned)(tid + e * nthr)] = cscale(o[e], scale);
+      for (int e = 0; e < E; ++e) {
+        const int idx = tid + e * nthr;
+        b[(unsigned)((idx >> lL) * ors + (idx & (L - 1)))] = cscale(o[e], scale);
+      }
     } else {
       float2* b = out + bo + c0;
       {
-        const unsigned f_lane = fresh(lane);
+        const unsigned f_lane = fresh((unsigned)(j * ors + c));
+        const unsigned oqs = (unsigned)(TPT * ors);
 #pragma unroll
-        for (int q = 0; q < E; ++q) b[f_lane + q * qs] = cscale(a[q], scale);
+        for (int q = 0; q < E; ++q) b[f_lane + q * oqs] = cscale(a[q], scale);
       }
     }
     if constexpr (PF) {
@@ -1239,7 +1245,8 @@ struct ColsGrad {
 template <int LG>
 struct ColsStrided {
   static hipError_t run(bool inv, bool twt, const float2* in, float2* out, int64_t batch, int C, int w, float scale,
-                        const float2* tlo, const float2* thi, int h, const Launch& lc) {
+                        const float2* tlo, const float2* thi, int h, int64_t ib, int irs, int64_t ob, int ors,
+                        const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = C / w;
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
@@ -1248,9 +1255,9 @@ struct ColsStrided {
     const int lt = ilog2c(tiles);
     if (inv)
       return go(k_cols_strided<L, true>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
-                scale, tlo, thi, h, tw);
+                scale, tlo, thi, h, tw, ib, irs, ob, ors);
     return go(k_cols_strided<L, false>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
-              scale, tlo, thi, h, tw);
+              scale, tlo, thi, h, tw, ib, irs, ob, ors);
   }
 };
 
@@ -1289,7 +1296,8 @@ struct ColsStrided {
     return ColsGrad<K>::run(ws, save, mask, part, nimg, groups, M, rb, bs, w, w_lin, w_sq, lc);
 #define FFTMI_CASE_ColsStrided(K) \
   case K:                         \
-    return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_lo, tw_hi, h, lc);
+    return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_lo, tw_hi, h, in_bstride, \
+                               in_rstride, out_bstride, out_rstride, lc);
 
 hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void* out, bool out_f32, int64_t rows,
                           float scale, const Launch& lc) {
@@ -1451,7 +1459,8 @@ hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int grou
 
 hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,
                                int64_t batch, int C, int w, float scale, const float2* tw_lo, const float2* tw_hi,
-                               int h, const Launch& lc) {
+                               int h, int64_t in_bstride, int in_rstride, int64_t out_bstride, int out_rstride,
+                               const Launch& lc) {
   FFTMI_DISPATCH(ColsStrided, log2L)
 }
 

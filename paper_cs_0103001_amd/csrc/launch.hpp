@@ -114,13 +114,16 @@ hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, con
 // grad = sum over g of part[g] (n floats each, n % 4 == 0), in group order.
 hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int groups, hipStream_t stream);
 
-// Strided column pass of the four-step long 1D transform over a row-major
-// [L][C] matrix per batch entry, tiles of w columns.  twiddle_transpose: pass
-// one (multiply by W_N^{k1 n2}, N = L*C, two-level tables lo/hi with split h,
-// and store transposed as [C][L]); otherwise pass two (store [L][C]).
+// Strided column pass of the four-step long 1D transform over an [L][C]
+// matrix per batch entry (row r of entry b at in + b*in_bstride +
+// r*in_rstride), tiles of w columns.  twiddle_transpose: pass one (multiply by
+// W_N^{k1 n2}, N = L*C, two-level tables lo/hi with split h, and store column c
+// as the contiguous row out + b*out_bstride + c*out_rstride); otherwise pass
+// two (store [L][C] with row stride out_rstride).
 hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,
                                int64_t batch, int C, int w, float scale, const float2* tw_lo, const float2* tw_hi,
-                               int h, const Launch& lc);
+                               int h, int64_t in_bstride, int in_rstride, int64_t out_bstride, int out_rstride,
+                               const Launch& lc);
 
 // Workgroups of a persistent launch.  With k = ceil(ntiles / resident) tiles
 // for the busiest workgroup, ceil(ntiles / k) workgroups finish in the same

@@ -51,6 +51,7 @@ struct fftmi_plan {
   // rank 1 beyond one LDS pass: four-step split N = N1 * N2
   bool fourstep = false;
   int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1, tw_h = 0;
+  int fs_rs = 0;  // row stride of the [N2][N1] intermediate (N1 + pad)
   const float2* tw_lo = nullptr;
   const float2* tw_hi = nullptr;
   size_t ws_bytes = 0, spec_bytes = 0;
@@ -71,6 +72,8 @@ void plan_unregister(fftmi_plan* p);
 // Pad (elements) added to a blocked layout's block stride of `stride`
 // elements: 32 when the stride is a multiple of 4 KiB, else 0.
 int64_t block_pad(int64_t stride);
+// Pad (elements) of the four-step intermediate's rows of 2^log_n1 entries.
+int fourstep_pad(int log_n1);
 
 // Widest power-of-two column tile (<= wmax, <= cols) that fits one workgroup.
 int widest_cols_tile(int log2L, int cols, int wmax);
