@@ -25,6 +25,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "4096^2 FFT-filter-IFFT GB/s (% HBM peak); batched, fwd+bwd vs plain"
 HBM_PEAK_GBS = 8000.0
+# the sections after the headline, in the order they run
+SECTIONS = ("copy", "half_spectrum", "cold", "batched", "fwd_bwd", "sweep_1d", "ragged")
 # untimed wall time each section after the headline runs before timing
 WARM_MS = 60.0
 N = M = 4096
@@ -120,6 +122,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--skip-extra", action="store_true", help="only the plain headline and its passes")
+    ap.add_argument("--only", choices=SECTIONS, default=None,
+                    help="the plain headline and this one extra section (for a profiler run of one workload)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device copy five times (counter calibration) and exit")
     args = ap.parse_args()
@@ -192,9 +196,13 @@ def main():
     }
     del x, out, ws
 
-    if not args.skip_extra:
+    def want(section):
+        return not args.skip_extra and args.only in (None, section)
+
+    if want("copy"):
         result["copy_GBs"] = round(copy_probe(torch, dev, 1 << 30, 10), 1)
 
+    if want("half_spectrum"):
         # ------------------------------------------------ half-spectrum variant
         # the same 4096^2 filter through FFT_REAL_EVEN (real image, even mask):
         # bytes per pixel 4+4, 4+4, 4+4 (f32 out) or 4+8 (c64 out)
@@ -215,6 +223,7 @@ def main():
                                                  "with the headline only")
         del x
 
+    if want("cold"):
         # --------------------------------------------------------- cold cache
         flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         x = torch.from_numpy(img).to(dev)
@@ -236,6 +245,7 @@ def main():
                           "note": "1 GiB buffer rewritten before each single-image run"}
         del flush, x, out, ws
 
+    if want("batched"):
         # ------------------------------------------------------------ batched
         Bn = synth.CONFIGS["image_4096"]["batched"]
         log("generating batch of %d images" % Bn)
@@ -250,9 +260,12 @@ def main():
         gbs_b = Bn * bytes_step / (msb * 1e-3) / 1e9
         result["batched"] = {"batch": Bn, "ms_per_step": round(msb, 4), "GB/s": round(gbs_b, 1),
                              "per_image_ms": round(msb / Bn, 4), "vs_plain": round(gbs_b / value, 3),
-                             "hbm_frac": round(gbs_b / HBM_PEAK_GBS, 4)}
+                             "hbm_frac": round(gbs_b / HBM_PEAK_GBS, 4),
+                             "ns_per_px": round(msb * 1e6 / (Bn * px), 4),
+                             "ns_per_px_plain_4096": round(ms * 1e6 / px, 4)}
         del xb, ob, wsb
 
+    if want("fwd_bwd"):
         # ----------------------------------------------------- forward+backward
         from paper_cs_0103001_amd.autograd import fft_filter_mse
         c4 = synth.CONFIGS["learn_1024"]
@@ -294,11 +307,9 @@ def main():
                              "time_vs_plain_same_batch": round(ms_fb / ms_pl, 3),
                              "ns_per_px": round(ms_fb * 1e6 / pxl, 4),
                              "ns_per_px_plain_4096": round(ms * 1e6 / px, 4)}
-        result["batched"]["ns_per_px"] = round(msb * 1e6 / (Bn * px), 4)
-        result["batched"]["ns_per_px_plain_4096"] = round(ms * 1e6 / px, 4)
         del noisy, clean, ol, wsl
 
-    if not args.skip_extra:
+    if want("sweep_1d"):
         # ------------------------------------------------------------ 1D sweep
         # forward transforms of complex64 signals, 256 MiB per batch (2^25
         # points), N = 2^10 .. 2^22; GB/s counts one read and one write of the
@@ -319,6 +330,7 @@ def main():
                                                                "N > 2^14 takes two strided passes"}
         del xs, ys
 
+    if want("ragged"):
         # ------------------------------------------------------------- ragged
         sizes = synth.ragged_sizes()
         log("generating the ragged batch (%d images)" % len(sizes))

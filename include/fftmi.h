@@ -107,8 +107,9 @@ typedef struct fftmi_plan* fft_plan_t;
 int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint32_t flags);
 
 /* Bytes of device workspace an exec/filter call on this plan needs (may be 0).
- * The caller allocates it (256-byte alignment is enough) and may reuse it
- * between calls on one stream. */
+ * The caller allocates it, aligned to at least 16 bytes (a call given a
+ * workspace that is not returns FFT_ERR_ARG; hipMalloc and torch give 256),
+ * and may reuse it between calls on one stream. */
 int fft_workspace_size(fft_plan_t plan, size_t* bytes);
 
 /* One transform of the whole batch: in -> out, out of place (in == out is

@@ -399,6 +399,7 @@ int fft2d_spectrum(fft_plan_t p, const void* in, float* magnitude, void* workspa
   if (p->batch == 0) return FFT_OK;
   if (!in || !magnitude) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
+  if (ws_misaligned(workspace)) return FFT_ERR_ARG;
   int rc = check_plan(p, nullptr);
   if (rc != FFT_OK) return rc;
   const bool in_f32 = p->flags & FFT_IN_REAL_F32;
@@ -447,6 +448,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
   if (p->batch == 0) return FFT_OK;
   if (!in || !out || in == out) return FFT_ERR_ARG;
   if (p->ws_bytes && !workspace) return FFT_ERR_WORKSPACE;
+  if (p->ws_bytes && ws_misaligned(workspace)) return FFT_ERR_ARG;
   int rc = check_plan(p, nullptr);
   if (rc != FFT_OK) return rc;
 
@@ -516,6 +518,7 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   if (p->batch == 0) return FFT_OK;
   if (((stages & 1) && !in) || ((stages & 4) && !out)) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
+  if (ws_misaligned(workspace)) return FFT_ERR_ARG;
   rc = check_plan(p, nullptr);
   if (rc != FFT_OK) return rc;
   const bool in_f32 = p->flags & FFT_IN_REAL_F32, out_f32 = p->flags & FFT_OUT_REAL_F32;
@@ -609,6 +612,7 @@ static int grad_impl(fftmi_plan* p, const void* in, const void* in2, const void*
   }
   if (!in || !spectrum) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
+  if (ws_misaligned(workspace)) return FFT_ERR_ARG;
   int rc = check_plan(p, nullptr);
   if (rc != FFT_OK) return rc;
   float2* ws = static_cast<float2*>(workspace);
@@ -658,6 +662,7 @@ int fft2d_filter_mse(fft_plan_t p, const float* x, const float* c, const float* 
   if (!loss) return FFT_ERR_ARG;
   if (p->batch > 0 && (!x || !c || !mask || !spectrum)) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
+  if (ws_misaligned(workspace)) return FFT_ERR_ARG;
   int rc = check_plan(p, nullptr);
   if (rc != FFT_OK) return rc;
   const hipStream_t st = static_cast<hipStream_t>(stream);

@@ -67,6 +67,8 @@ namespace fftmi {
 // Live-plan registry: lets every entry point reject freed or foreign handles.
 void plan_register(fftmi_plan* p);
 bool plan_live(const fftmi_plan* p);
+// The kernels store 16-byte vectors into the workspace.
+inline bool ws_misaligned(const void* ws) { return (reinterpret_cast<uintptr_t>(ws) & 15) != 0; }
 void plan_unregister(fftmi_plan* p);
 
 // Pad (elements) added to a blocked layout's block stride of `stride`

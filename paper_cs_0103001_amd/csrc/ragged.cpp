@@ -65,6 +65,9 @@ struct RaggedState {
   void* g_ws = nullptr;
   MaskArgs g_mask{};
   bool use_graph = true;
+  // real input: the first row pass takes the rows in pairs (twice the rows
+  // per tile)
+  bool in_f32 = false;
 };
 
 namespace {
@@ -128,7 +131,9 @@ int build_lists(RaggedState* r) {
       run.begin[p] = (int64_t)lists[p].size();
       for (int64_t i : idx) {
         const int64_t s = r->sizes[i];
-        const int per = std::max(1, r->sched.block / threads_per_transform((int)s));  // rows or columns per tile
+        // rows or columns per tile: one per transform, two per transform
+        // in the first row pass of real input
+        const int per = std::max(1, r->sched.block / threads_per_transform((int)s)) * (p == 0 && r->in_f32 ? 2 : 1);
         const int64_t tiles = (s + per - 1) / per;
         for (int64_t t = 0; t < tiles; ++t) lists[p].push_back(make_int2((int)i, (int)t));
       }
@@ -329,6 +334,7 @@ int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32
   int rc = device_tables(dev, &p->tables);
   if (rc != FFT_OK) return rc;
   r->sizes.assign(sizes, sizes + count);
+  r->in_f32 = (flags & FFT_IN_REAL_F32) != 0;
   for (int64_t s : r->sizes) {
     r->total += s * s;
     r->ws_total += ws_elems_for(s);
@@ -365,6 +371,7 @@ int fft2d_filter_ragged(fft_plan_t p, const void* in, void* out, const fft_mask*
   if (p->batch == 0) return FFT_OK;
   if (!in || !out) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
+  if (ws_misaligned(workspace)) return FFT_ERR_ARG;
   rc = plan_check(p, nullptr);
   if (rc != FFT_OK) return rc;
   const hipStream_t st = static_cast<hipStream_t>(stream);
@@ -407,6 +414,7 @@ int fft_plan_tune(fft_plan_t p, const void* in, void* out, const fft_mask* mask,
   if (p->batch == 0) return FFT_OK;
   if (!in || !out) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
+  if (ws_misaligned(workspace)) return FFT_ERR_ARG;
   int rc = plan_check(p, nullptr);
   if (rc != FFT_OK) return rc;
   MaskArgs mk;

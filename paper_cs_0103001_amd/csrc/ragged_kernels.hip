@@ -52,10 +52,10 @@ __device__ __forceinline__ void rg_tw_lds(const float2* __restrict__ tw) {
   }
 }
 
-// Forward row transforms of one tile: rows u = t*R + r of the image, f32 or
-// c64 input, scaled, stored into the blocked workspace.
-template <int L, bool IN_F32>
-__device__ __forceinline__ void rg_rows_fwd(const void* __restrict__ in, float2* __restrict__ ws,
+// Forward row transforms of one tile of complex input: rows u = t*R + r of
+// the image, scaled, stored into the blocked workspace.
+template <int L>
+__device__ __forceinline__ void rg_rows_fwd(const float2* __restrict__ in, float2* __restrict__ ws,
                                             const RaggedImage& im, int t, const float2* __restrict__ tw, char* lds,
                                             float scale) {
   constexpr int E = elems_per_thread(L), TPT = L / E;
@@ -64,16 +64,10 @@ __device__ __forceinline__ void rg_rows_fwd(const void* __restrict__ in, float2*
   const int u = t * R + r;
   const bool ok = u < L;
   char* x = lds + r * lds_region_bytes(L, R);
+  const float2* src = in + im.off + (int64_t)(ok ? u : 0) * L;
   float2 a[E];
-  if constexpr (IN_F32) {
-    const float* src = static_cast<const float*>(in) + im.off + (int64_t)(ok ? u : 0) * L;
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = make_float2(ok ? __ldg(src + j + q * TPT) : 0.f, 0.f);
-  } else {
-    const float2* src = static_cast<const float2*>(in) + im.off + (int64_t)(ok ? u : 0) * L;
-#pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + j + q * TPT) : make_float2(0.f, 0.f);
-  }
+  for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + j + q * TPT) : make_float2(0.f, 0.f);
   float2 twr[reg_tw_count_mix<L>()];
   load_twiddles_reg_mix<L>(twr, j, tw);
   fft_reg<L, false, kTwMix>(a, j, x, twr);
@@ -82,6 +76,65 @@ __device__ __forceinline__ void rg_rows_fwd(const void* __restrict__ in, float2*
     float2* dst = ws + im.ws_off + (int64_t)(u / rb) * im.bs + (u % rb);
 #pragma unroll
     for (int q = 0; q < E; ++q) dst[(j + q * TPT) * rb] = cscale(a[q], scale);
+  }
+}
+
+// The same for real input, two rows per transform: rows u = 2 (t*R + r) and
+// u + 1 packed as z = f_u + i f_(u+1).  The two spectra follow from the
+// Hermitian symmetry of a real row's DFT, F_u(k) = (Z(k) + conj Z(-k)) / 2
+// and F_(u+1)(k) = (Z(k) - conj Z(-k)) / 2i.  Every Z goes through LDS, and
+// the stores are remapped so that consecutive lanes take consecutive pairs
+// of one column: with rb >= 2 a pair is two neighbouring entries of a block,
+// written as one float4.
+template <int L>
+__device__ __forceinline__ void rg_rows_fwd_pair(const float* __restrict__ in, float2* __restrict__ ws,
+                                                 const RaggedImage& im, int t, const float2* __restrict__ tw,
+                                                 char* lds, float scale) {
+  constexpr int E = elems_per_thread(L), TPT = L / E;
+  const int R = (int)blockDim.x / TPT;
+  const int rbytes = lds_region_bytes(L, R);
+  const int tid = threadIdx.x, r = tid / TPT, j = tid - r * TPT;
+  const int u = 2 * (t * R + r);
+  char* x = lds + r * rbytes;
+  {
+    const bool ok = u < L, ok2 = u + 1 < L;
+    const float* src = in + im.off + (int64_t)(ok ? u : 0) * L;
+    float2 a[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+      a[q] = make_float2(ok ? __ldg(src + j + q * TPT) : 0.f, ok2 ? __ldg(src + L + j + q * TPT) : 0.f);
+    float2 twr[reg_tw_count_mix<L>()];
+    load_twiddles_reg_mix<L>(twr, j, tw);
+    fft_reg<L, false, kTwMix>(a, j, x, twr);
+    lds_barrier();  // the transform's last readers of x are done
+    scatter_natural<L, kBoth>(a, j, x);
+    lds_barrier();
+  }
+  // store lanes: pair pp = tid % R of the tile, columns v = tid / R + i*TPT
+  const int pp = tid & (R - 1), v0 = tid / R;
+  const int up = 2 * (t * R + pp);
+  if (up >= L) return;
+  const bool two = up + 1 < L;
+  const float2* xs = reinterpret_cast<const float2*>(lds + pp * rbytes);
+  const float h = 0.5f * scale;
+  const int rb = im.rb;
+  float2* d0 = ws + im.ws_off + (int64_t)(up / rb) * im.bs + (up % rb);
+  float2* d1 = ws + im.ws_off + (int64_t)((up + 1) / rb) * im.bs + ((up + 1) % rb);
+  // one float4 per (pair, column) when the pair shares a block and the
+  // image's workspace starts on a 16-byte boundary (uniform per image)
+  const bool f4 = rb >= 2 && ((im.ws_off & 1) == 0);
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int v = v0 + i * TPT;
+    const float2 z = xs[lds_pad(v)];
+    const float2 zm = xs[lds_pad((L - v) & (L - 1))];
+    const float4 o = make_float4(h * (z.x + zm.x), h * (z.y - zm.y), h * (z.y + zm.y), h * (zm.x - z.x));
+    if (f4) {
+      *reinterpret_cast<float4*>(d0 + v * rb) = o;
+    } else {
+      d0[v * rb] = make_float2(o.x, o.y);
+      if (two) d1[v * rb] = make_float2(o.z, o.w);
+    }
   }
 }
 
@@ -176,7 +229,10 @@ __global__ __launch_bounds__(kRaggedMaxBlock) __attribute__((amdgpu_waves_per_eu
       rg_tw_lds<1 << K>(tw.p[K]);                                         \
       cur_lg = im.lg;                                                     \
     }                                                                     \
-    rg_rows_fwd<1 << K, IN_F32>(in, ws, im, tl.y, tw.p[K], lds, sc);      \
+    if constexpr (IN_F32)                                                 \
+      rg_rows_fwd_pair<1 << K>(static_cast<const float*>(in), ws, im, tl.y, tw.p[K], lds, sc); \
+    else                                                                  \
+      rg_rows_fwd<1 << K>(static_cast<const float2*>(in), ws, im, tl.y, tw.p[K], lds, sc); \
     break;
       FFTMI_RG_CASES(FFTMI_RG_ROWS_FWD)
 #undef FFTMI_RG_ROWS_FWD

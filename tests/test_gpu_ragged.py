@@ -162,3 +162,39 @@ def test_ragged_workload_512_sampled():
         ref = oracle.filter2(im, oracle.mask_gaussian(s, s, SIGMA_F), threads=8)
         err = rel_l2(a[offs[i]:offs[i + 1]].reshape(s, s), ref, 2)
         assert err < TOL, (i, s, err)
+
+
+def test_misaligned_workspace_rejected():
+    """The kernels store 16-byte vectors into the workspace: a workspace
+    pointer off a 16-byte boundary is refused with FFT_ERR_ARG before any
+    launch, by the uniform, 1D and ragged entry points alike."""
+    import ctypes
+    import torch
+    from paper_cs_0103001_amd import _binding as B
+    from paper_cs_0103001_amd import api
+    dev = torch.device("cuda", 0)
+    st = api._stream(dev)
+    mk = B.make_mask(kind="gaussian", sigma_f=SIGMA_F)
+
+    def refused(call, ws):
+        bad = ctypes.c_void_p(ws.data_ptr() + 8)
+        with pytest.raises(B.FFTError) as ei:
+            call(bad)
+        assert ei.value.code == B.FFT_ERR_ARG
+
+    x = torch.zeros((64, 64), dtype=torch.float32, device=dev)
+    o = torch.empty((64, 64), dtype=torch.complex64, device=dev)
+    p2 = api.Plan(2, (64, 64), 1, B.FFT_IN_REAL_F32, dev)
+    ws2 = torch.empty(p2.workspace_bytes + 64, dtype=torch.uint8, device=dev)
+    refused(lambda w: B.fft2d_filter(p2.h, api._ptr(x), api._ptr(o), mk, w, st), ws2)
+    xc = torch.zeros((3, 1 << 15), dtype=torch.complex64, device=dev)
+    oc = torch.empty_like(xc)
+    p1 = api.Plan(1, (1 << 15,), 3, 0, dev)
+    ws1 = torch.empty(p1.workspace_bytes + 64, dtype=torch.uint8, device=dev)
+    refused(lambda w: B.fft_exec(p1.h, api._ptr(xc), api._ptr(oc), w, B.FFT_FORWARD, st), ws1)
+    sizes = [64, 32, 1]
+    xr = torch.zeros(sum(s * s for s in sizes), dtype=torch.float32, device=dev)
+    orr = torch.empty(xr.numel(), dtype=torch.complex64, device=dev)
+    pr = api.get_plan(0, (), len(sizes), B.FFT_IN_REAL_F32, dev, ragged_sizes=sizes)
+    wsr = torch.empty(pr.workspace_bytes + 64, dtype=torch.uint8, device=dev)
+    refused(lambda w: B.fft2d_filter_ragged(pr.h, api._ptr(xr), api._ptr(orr), mk, w, st), wsr)
