@@ -179,12 +179,37 @@ __device__ __forceinline__ void rg_rows_inv(const float2* __restrict__ ws, void*
   const int tid = threadIdx.x, r = tid / TPT, j = tid - r * TPT;
   const int u = t * R + r;
   const bool ok = u < L;
-  char* x = lds + r * lds_region_bytes(L, R);
+  const int rbytes = lds_region_bytes(L, R);
+  char* x = lds + r * rbytes;
   const int rb = im.rb;
-  const float2* src = ws + im.ws_off + (int64_t)((ok ? u : 0) / rb) * im.bs + ((ok ? u : 0) % rb);
   float2 a[E];
+  if (rb >= 2 && R >= 2 && (im.ws_off & 1) == 0) {
+    // rows in pairs (neighbours in a block) as float4s, consecutive lanes
+    // on consecutive pairs of one column, handed to the transforms through
+    // LDS (R is a power of two)
+    const int P = R >> 1;
+    const int pp = tid & (P - 1), v0 = tid / P;
+    const int up = t * R + 2 * pp;
+    lds_barrier();  // the previous tile's readers of the regions are done
+    if (up < L) {
+      const float4* src = reinterpret_cast<const float4*>(ws + im.ws_off + (int64_t)(up / rb) * im.bs + (up % rb));
+      float2* x0 = reinterpret_cast<float2*>(lds + (2 * pp) * rbytes);
+      float2* x1 = reinterpret_cast<float2*>(lds + (2 * pp + 1) * rbytes);
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + (j + q * TPT) * rb) : make_float2(0.f, 0.f);
+      for (int i = 0; i < E / 2; ++i) {
+        const int v = v0 + i * 2 * TPT;
+        const float4 y = __ldg(src + v * (rb >> 1));
+        x0[lds_pad(v)] = make_float2(y.x, y.y);
+        x1[lds_pad(v)] = make_float2(y.z, y.w);
+      }
+    }
+    lds_barrier();
+    gather_natural<L, kBoth>(a, j, x);
+  } else {
+    const float2* src = ws + im.ws_off + (int64_t)((ok ? u : 0) / rb) * im.bs + ((ok ? u : 0) % rb);
+#pragma unroll
+    for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + (j + q * TPT) * rb) : make_float2(0.f, 0.f);
+  }
   float2 twr[reg_tw_count_mix<L>()];
   load_twiddles_reg_mix<L>(twr, j, tw);
   fft_reg<L, true, kTwMix>(a, j, x, twr);
