@@ -43,8 +43,7 @@ struct DevTables {
   float2* blob = nullptr;
   int64_t off[kMaxLog2Row + 1] = {};
   int64_t off_lds[kMaxLog2Row + 1] = {};  // LDS-layout copies, after the global-layout tables
-  std::map<int, std::pair<float2*, float2*>> fourstep;  // log2 N -> (lo, hi)
-  std::map<int, int> fourstep_h;
+  std::map<int, float2*> fourstep;  // log2 N -> [N2][N1] factors of the four-step split
 };
 
 namespace {
@@ -131,16 +130,18 @@ void plan_unregister(fftmi_plan* p) {
   g_plans.erase(p);
 }
 
-// Two-level twiddles of the long transform: W_N^t = lo[t mod 2^h] * hi[t >> h].
-int fourstep_tables(DevTables* t, int log2N, const float2** lo, const float2** hi, int* h) {
+// Factors of the four-step split N = N1 N2 (N1 = 2^log2N1), laid out as the
+// first pass stores its output: entry n2*N1 + k1 is W_N^{k1 n2}, from the
+// exact integer k1 n2 mod N in FP64, rounded once.
+int fourstep_tables(DevTables* t, int log2N, int log2N1, const float2** tab) {
   std::lock_guard<std::mutex> lk(g_mu);
   auto it = t->fourstep.find(log2N);
   if (it == t->fourstep.end()) {
-    const int hh = (log2N + 1) / 2;
-    const int64_t N = int64_t(1) << log2N, nlo = int64_t(1) << hh, nhi = N >> hh;
-    std::vector<float2> host((size_t)(nlo + nhi));
-    for (int64_t i = 0; i < nlo; ++i) host[(size_t)i] = z_factor(i, N);
-    for (int64_t i = 0; i < nhi; ++i) host[(size_t)(nlo + i)] = z_factor(i << hh, N);
+    const int64_t N = int64_t(1) << log2N, n1 = int64_t(1) << log2N1, n2 = N / n1;
+    std::vector<float2> z((size_t)N), host((size_t)N);
+    for (int64_t i = 0; i < N; ++i) z[(size_t)i] = z_factor(i, N);
+    for (int64_t b = 0; b < n2; ++b)
+      for (int64_t k = 0; k < n1; ++k) host[(size_t)(b * n1 + k)] = z[(size_t)((k * b) & (N - 1))];
     void* d = nullptr;
     hipError_t e = hipMalloc(&d, host.size() * sizeof(float2));
     if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_NOMEM : hip_fail(e);
@@ -149,13 +150,9 @@ int fourstep_tables(DevTables* t, int log2N, const float2** lo, const float2** h
       (void)hipFree(d);
       return hip_fail(e);
     }
-    float2* p = static_cast<float2*>(d);
-    it = t->fourstep.emplace(log2N, std::make_pair(p, p + nlo)).first;
-    t->fourstep_h[log2N] = hh;
+    it = t->fourstep.emplace(log2N, static_cast<float2*>(d)).first;
   }
-  *lo = it->second.first;
-  *hi = it->second.second;
-  *h = t->fourstep_h[log2N];
+  *tab = it->second;
   return FFT_OK;
 }
 
@@ -317,7 +314,7 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       }
       p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, wmax);
       p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, wmax);
-      rc = fourstep_tables(t, p->log_n, &p->tw_lo, &p->tw_hi, &p->tw_h);
+      rc = fourstep_tables(t, p->log_n, p->log_n1, &p->tw_fs);
       if (rc != FFT_OK) return rc;
       // the intermediate [N2][N1] rows get a padded stride, so that the
       // second pass's column reads do not all land on the same channels
@@ -474,11 +471,11 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
     const int64_t wsb = (int64_t)n2 * p->fs_rs;
     Launch l1 = launch_for(st, p->tables, p->log_n1);
     e = launch_cols_strided(p->log_n1, inv_tw, true, static_cast<const float2*>(in), ws, p->batch, n2, p->w1, 1.0f,
-                            p->tw_lo, p->tw_hi, p->tw_h, p->n, n2, wsb, p->fs_rs, l1);
+                            p->tw_fs, p->n, n2, wsb, p->fs_rs, l1);
     if (e != hipSuccess) return hip_fail(e);
     Launch l2 = launch_for(st, p->tables, p->log_n2);
     e = launch_cols_strided(p->log_n2, inv_tw, false, ws, static_cast<float2*>(out), p->batch, n1, p->w2, scale,
-                            nullptr, nullptr, 0, wsb, p->fs_rs, p->n, n1, l2);
+                            nullptr, wsb, p->fs_rs, p->n, n1, l2);
     return e == hipSuccess ? FFT_OK : hip_fail(e);
   }
 

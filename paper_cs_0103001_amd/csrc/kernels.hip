@@ -838,14 +838,14 @@ __global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ p
 // ============================================================== kernel E
 // Strided column pass over an [L][C] matrix per batch entry (the four-step
 // long 1D transform): row r of entry b starts at b*ib + r*irs.
-// twiddle_transpose: pass one (multiply by W_N^{k1 n2} from two-level tables
-// and store transposed, column c as the row of L entries at b*ob + c*ors);
-// otherwise pass two (store [L][C] with row stride ors).
+// twiddle_transpose: pass one (store transposed, column c as the row of L
+// entries at b*ob + c*ors, each entry times W_N^{k1 n2} = tfs[n2*L + k1],
+// read in the same order as the stores); otherwise pass two (store [L][C]
+// with row stride ors).
 template <int L, bool INV>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __restrict__ in, float2* __restrict__ out,
                                                        int C, int w, int ltiles, int ntiles, int twiddle_transpose,
-                                                       float scale, const float2* __restrict__ tlo,
-                                                       const float2* __restrict__ thi, int h,
+                                                       float scale, const float2* __restrict__ tfs,
                                                        const float2* __restrict__ tws, int64_t ib, int irs,
                                                        int64_t ob, int ors) {
   using S = Shape<L>;
@@ -886,15 +886,6 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
     const int c0 = (t & tmask) * w;
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
     if (twiddle_transpose) {
-      const int n2 = c0 + c;
-      const int lomask = (1 << h) - 1;
-#pragma unroll
-      for (int q = 0; q < E; ++q) {
-        const int tt = (j + q * TPT) * n2;  // < N <= 2^24, exact
-        const float2 lo = tlo[tt & lomask], hi = thi[tt >> h];
-        const float2 wv = make_float2(lo.x * hi.x - lo.y * hi.y, lo.x * hi.y + lo.y * hi.x);
-        a[q] = cmul_tw<INV>(a[q], wv);
-      }
       // transposed store through LDS: out[n2][k1], contiguous along k1
       const int nthr = w * TPT;
       const int lL = ilog2_pow2(L);
@@ -927,10 +918,12 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
         }
       }
       float2* b = out + bo + (int64_t)c0 * ors;
+      const float2* tf = tfs + (int64_t)c0 * L;  // rows n2 = c0 .. c0 + w - 1
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int idx = tid + e * nthr;
-        b[(unsigned)((idx >> lL) * ors + (idx & (L - 1)))] = cscale(o[e], scale);
+        const float2 wv = tf[(unsigned)idx];  // W_N^{k1 n2}, k1 = idx % L, n2 = c0 + idx / L
+        b[(unsigned)((idx >> lL) * ors + (idx & (L - 1)))] = cscale(cmul_tw<INV>(o[e], wv), scale);
       }
     } else {
       float2* b = out + bo + c0;
@@ -1245,8 +1238,7 @@ struct ColsGrad {
 template <int LG>
 struct ColsStrided {
   static hipError_t run(bool inv, bool twt, const float2* in, float2* out, int64_t batch, int C, int w, float scale,
-                        const float2* tlo, const float2* thi, int h, int64_t ib, int irs, int64_t ob, int ors,
-                        const Launch& lc) {
+                        const float2* tfs, int64_t ib, int irs, int64_t ob, int ors, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     const int tiles = C / w;
     const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
@@ -1255,9 +1247,9 @@ struct ColsStrided {
     const int lt = ilog2c(tiles);
     if (inv)
       return go(k_cols_strided<L, true>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
-                scale, tlo, thi, h, tw, ib, irs, ob, ors);
+                scale, tfs, tw, ib, irs, ob, ors);
     return go(k_cols_strided<L, false>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
-              scale, tlo, thi, h, tw, ib, irs, ob, ors);
+              scale, tfs, tw, ib, irs, ob, ors);
   }
 };
 
@@ -1296,8 +1288,8 @@ struct ColsStrided {
     return ColsGrad<K>::run(ws, save, mask, part, nimg, groups, M, rb, bs, w, w_lin, w_sq, lc);
 #define FFTMI_CASE_ColsStrided(K) \
   case K:                         \
-    return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_lo, tw_hi, h, in_bstride, \
-                               in_rstride, out_bstride, out_rstride, lc);
+    return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_fs, in_bstride, in_rstride, \
+                               out_bstride, out_rstride, lc);
 
 hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void* out, bool out_f32, int64_t rows,
                           float scale, const Launch& lc) {
@@ -1458,9 +1450,8 @@ hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int grou
 }
 
 hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,
-                               int64_t batch, int C, int w, float scale, const float2* tw_lo, const float2* tw_hi,
-                               int h, int64_t in_bstride, int in_rstride, int64_t out_bstride, int out_rstride,
-                               const Launch& lc) {
+                               int64_t batch, int C, int w, float scale, const float2* tw_fs, int64_t in_bstride,
+                               int in_rstride, int64_t out_bstride, int out_rstride, const Launch& lc) {
   FFTMI_DISPATCH(ColsStrided, log2L)
 }
 

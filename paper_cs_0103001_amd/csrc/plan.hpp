@@ -22,7 +22,7 @@ int hip_fail(hipError_t e);
 int device_tables(int dev, DevTables** out);
 const float2* blob_for(const DevTables* t, int log2L);
 const float2* lds_blob_for(const DevTables* t, int log2L);
-int fourstep_tables(DevTables* t, int log2N, const float2** lo, const float2** hi, int* h);
+int fourstep_tables(DevTables* t, int log2N, int log2N1, const float2** tab);
 
 }  // namespace fftmi
 
@@ -50,10 +50,9 @@ struct fftmi_plan {
   size_t pad_in_off = 0, pad_out_off = 0;
   // rank 1 beyond one LDS pass: four-step split N = N1 * N2
   bool fourstep = false;
-  int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1, tw_h = 0;
+  int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1;
   int fs_rs = 0;  // row stride of the [N2][N1] intermediate (N1 + pad)
-  const float2* tw_lo = nullptr;
-  const float2* tw_hi = nullptr;
+  const float2* tw_fs = nullptr;  // [N2][N1] factors W_N^{k1 n2}
   size_t ws_bytes = 0, spec_bytes = 0;
   // rank 2: image groups of the mask-gradient column pass, and the workspace
   // offsets of their partial sums and of the fused MSE forward's per-tile sums
