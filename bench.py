@@ -68,6 +68,26 @@ def read_traffic(stage):
     return int(float(v)) if v else None
 
 
+def cpu_model():
+    """Model name of the host CPU (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def copy_probe(torch, dev, nbytes=256 << 20, reps=5):
     """A plain device-to-device copy of known size (the counter calibration
     and the measured-bandwidth context)."""
@@ -77,7 +97,7 @@ def copy_probe(torch, dev, nbytes=256 << 20, reps=5):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def pass_ms(torch, B, h, xp, op, mk, wp, st, steps, warmup):
+def pass_ms(torch, B, h, xp, op, mk, wp, st, steps, warmup, warm_ms=0.0):
     """Average duration of each pass of fft2d_filter: the pass's kernel
     launched `steps` times back to back (after `warmup` untimed launches)
     between two HIP events on the launch stream.  Pass 1 rewrites the
@@ -86,7 +106,7 @@ def pass_ms(torch, B, h, xp, op, mk, wp, st, steps, warmup):
     kernel-trace averages agree (profiles/kernels_image_4096.txt)."""
     out = {}
     for p in (0, 1, 2):
-        out[p] = timed(torch, lambda: B.fft2d_filter_stage(h, p, xp, op, mk, wp, st), steps, warmup)
+        out[p] = timed(torch, lambda: B.fft2d_filter_stage(h, p, xp, op, mk, wp, st), steps, warmup, warm_ms)
     return out
 
 
@@ -163,14 +183,14 @@ def main():
     def step():
         B.fft2d_filter(plan.h, xp, op, mk, wp, st)
 
-    log("timing plain 4096^2 (%d warmup, %d steps)" % (W, K))
-    ms = timed(torch, step, K, W)
+    log("timing plain 4096^2 (%d warmup, %d steps, >= %.0f ms untimed)" % (W, K, WARM_MS))
+    ms = timed(torch, step, K, W, WARM_MS)
     px = N * M
     bytes_step = 44 * px
     value = bytes_step / (ms * 1e-3) / 1e9
 
     # per-pass kernel durations: each pass's launches back to back
-    stage_ms = pass_ms(torch, B, plan.h, xp, op, mk, wp, st, K, W)
+    stage_ms = pass_ms(torch, B, plan.h, xp, op, mk, wp, st, K, W, WARM_MS / 2)
     dom = max(stage_ms, key=lambda k: stage_ms[k])
     dom_bytes = PASS_BYTES[dom] * px
     achieved = dom_bytes / (stage_ms[dom] * 1e-3) / 1e9
@@ -188,9 +208,10 @@ def main():
                                "complex64 out", "N": N, "M": M, "batch": 1, "bytes_per_step": bytes_step,
                    "byte_model": "44 B/px = (4+8) rows + (8+8) columns + (8+8) inverse rows"},
         "hbm_frac": round(value / HBM_PEAK_GBS, 4),
-        "timing": {"warmup_steps": W, "timed_steps": K,
-                   "note": "sustained clocks: the first ~100 steps after an idle GPU run 10-15% slower; "
-                           "the default warm-up (300 steps, ~45 ms) reaches the sustained state"},
+        "timing": {"warmup_steps": W, "timed_steps": K, "untimed_floor_ms": WARM_MS,
+                   "note": "sustained clocks: the first ~100 steps after an idle GPU run 10-15% slower; the "
+                           "untimed calls go on for at least untimed_floor_ms of wall time (whatever --warmup "
+                           "is) before the K timed steps, and each pass loop of passes_us for half of that"},
         "roofline": roofline,
         "passes_us": {PASS_NAMES[k]: round(v * 1e3, 2) for k, v in stage_ms.items()},
     }
@@ -360,19 +381,29 @@ def main():
     if not args.no_cpu:
         import oracle
         cores = oracle.default_threads()
-        log("timing the FP64 CPU oracle on %d threads" % cores)
         m64 = oracle.mask_butterworth(N, M, 0.15, 4)
-        # a bounded sample of about 10 s of host work, whole filter runs only
-        reps, t_total = 0, 0.0
-        while reps < 1 or (t_total < 10.0 and reps < 100):
-            t0 = time.perf_counter()
-            oracle.filter2(img, m64, threads=cores)
-            t_total += time.perf_counter() - t0
-            reps += 1
+
+        def sample(threads, budget_s, most):
+            """Whole filter2 runs until budget_s seconds of wall time (at least one)."""
+            reps, t_total = 0, 0.0
+            while reps < 1 or (t_total < budget_s and reps < most):
+                t0 = time.perf_counter()
+                oracle.filter2(img, m64, threads=threads)
+                t_total += time.perf_counter() - t0
+                reps += 1
+            return reps, t_total
+
+        log("timing the FP64 CPU oracle on %d threads" % cores)
+        reps, t_total = sample(cores, 8.0, 100)
         cpu_gbs = reps * bytes_step / t_total / 1e9
+        log("timing the FP64 CPU oracle on 1 thread")
+        reps1, t1 = sample(1, 0.0, 1)
         result["cpu_baseline"] = {"value": round(cpu_gbs, 4), "unit": "GB/s", "cores": cores, "kind": "oracle",
                                   "sample": "%d run(s) of the FP64 oracle filter2 on the 4096x4096 image "
-                                            "(44 B/px model), %.2f s" % (reps, t_total)}
+                                            "(44 B/px model), %.2f s on %d threads" % (reps, t_total, cores),
+                                  "single_thread": {"value": round(reps1 * bytes_step / t1 / 1e9, 4),
+                                                    "unit": "GB/s", "s_per_image": round(t1 / reps1, 3)},
+                                  "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
     print(json.dumps(result), flush=True)
 
 

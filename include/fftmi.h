@@ -66,8 +66,10 @@ extern "C" {
 #define FFT_NORM_PAPER 0x0u   /* the paper's scale factors, listed above (default) */
 #define FFT_NORM_NUMPY 0x4u   /* forward unscaled, inverse 1/(number of points) */
 /* Rank-2 plans for fft2d_filter on real images with masks even in
- * frequency, H(-u, -v) = H(u, v) (Gaussian, Butterworth, none, a disc
- * centred at 0 or N/2 by 0 or M/2): the 2D spectrum of a real image is
+ * frequency, H(-u, -v) = H(u, v) with bins taken modulo (N, M) (Gaussian,
+ * Butterworth, none, or a disc centred at (N/2, M/2); a disc evaluated on
+ * raw bin indices around any other centre is not even and is refused with
+ * FFT_ERR_UNSUPPORTED): the 2D spectrum of a real image is
  * Hermitian, so only columns 0 .. M/2 are carried (columns 0 and M/2 packed
  * into one complex column) and the result, which is real, comes from one
  * complex inverse transform per two rows.  Requires FFT_IN_REAL_F32, N >= 32
@@ -250,6 +252,16 @@ int fft_plan_tune(fft_plan_t plan, const void* in_packed, void* out_packed, cons
 
 /* The schedule a ragged plan uses (any pointer may be NULL). */
 int fft_plan_schedule(fft_plan_t plan, int* block, int* wg_cap, int64_t* chunk_bytes, int* order);
+
+/* Layout of a rank-2 plan (any pointer may be NULL), for callers that check
+ * which kernel path a batch takes: rows per block of the blocked workspace
+ * layout, columns per column-pass tile, images per chunk of fft2d_filter (its
+ * three passes run chunk by chunk), and the number of runs of consecutive
+ * images whose mask-gradient sums are formed separately and then added in run
+ * order (images per run = ceil(batch / runs)).  FFT_ERR_STATE for other plan
+ * kinds. */
+int fft_plan_layout(fft_plan_t plan, int* rows_per_block, int* cols_per_tile, int64_t* chunk_images,
+                    int* grad_runs);
 
 /* Release a plan (and any graph it instantiated).  NULL is a no-op. */
 int fft_plan_destroy(fft_plan_t plan);

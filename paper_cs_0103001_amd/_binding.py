@@ -74,6 +74,8 @@ _SIGS = {
                                          _I64P, ctypes.POINTER(ctypes.c_int)]),
     "fft_plan_padded": (ctypes.c_int, [ctypes.POINTER(_P), _I64P, ctypes.c_int64, ctypes.c_uint32]),
     "fft2d_spectrum": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "fft_plan_layout": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _I64P,
+                                       ctypes.POINTER(ctypes.c_int)]),
     "fft_plan_destroy": (ctypes.c_int, [_P]),
     "fft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fft_version": (ctypes.c_int, []),
@@ -202,6 +204,14 @@ def fft_plan_schedule(plan):
     check(lib().fft_plan_schedule(plan, ctypes.byref(b), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(o)),
           "fft_plan_schedule")
     return {"block": b.value, "wg_cap": c.value, "chunk_bytes": ch.value, "order": o.value}
+
+
+def fft_plan_layout(plan):
+    rb, w, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ch = ctypes.c_int64()
+    check(lib().fft_plan_layout(plan, ctypes.byref(rb), ctypes.byref(w), ctypes.byref(ch), ctypes.byref(g)),
+          "fft_plan_layout")
+    return {"rows_per_block": rb.value, "cols_per_tile": w.value, "chunk_images": ch.value, "grad_runs": g.value}
 
 
 def fft_plan_destroy(plan):

@@ -200,12 +200,42 @@ def spectrum(x, norm="paper"):
     return out
 
 
+def _check_images(x, what="x"):
+    if not isinstance(x, torch.Tensor):
+        raise TypeError("%s must be a tensor" % what)
+    if x.dim() < 2 or x.shape[-2] < 1 or x.shape[-1] < 1:
+        raise ValueError("%s must have at least two non-empty axes, got %s" % (what, tuple(x.shape)))
+
+
+def _check_mask_tensor(mask, N, M, device):
+    """A learnable mask: float32 [N][M] on the images' device."""
+    if not isinstance(mask, torch.Tensor):
+        raise TypeError("mask must be a tensor")
+    if mask.dtype != torch.float32 or tuple(mask.shape) != (N, M):
+        raise ValueError("mask must be float32 [%d, %d], got %s %s" % (N, M, mask.dtype, tuple(mask.shape)))
+    if mask.device != device:
+        raise ValueError("mask is on %s, the images on %s" % (mask.device, device))
+
+
+def _check_spectrum(spectrum, plan, device):
+    """A saved spectrum from fft2d_filter(spectrum=True) or filter_mse for this plan's shape."""
+    if not isinstance(spectrum, torch.Tensor):
+        raise TypeError("spectrum must be a tensor")
+    if spectrum.device != device or not spectrum.is_contiguous():
+        raise ValueError("spectrum must be a contiguous tensor on %s" % device)
+    have = spectrum.numel() * spectrum.element_size()
+    if have < plan.spectrum_bytes:
+        raise ValueError("spectrum holds %d bytes, this batch's plan needs %d" % (have, plan.spectrum_bytes))
+
+
 def mask_grad(grad_y, spectrum, norm="paper"):
     """sum_b Re(conj(X_b) . (2D-IDFT^H grad_y_b)) for a saved spectrum X."""
+    _check_images(grad_y, "grad_y")
     g, _ = _prep(grad_y, allow_real=False)
     N, M = g.shape[-2], g.shape[-1]
     batch = g.numel() // (N * M)
     plan = get_plan(2, (N, M), batch, B.FFT_IN_C64 | _NORM[norm], g.device)
+    _check_spectrum(spectrum, plan, g.device)
     out = torch.empty((N, M), dtype=torch.float32, device=g.device)
     ws = plan.workspace()
     B.fft2d_filter_mask_grad(plan.h, _ptr(g), _ptr(spectrum), _ptr(out), _ptr(ws), _stream(g.device))
@@ -216,16 +246,21 @@ def mse_grad(x, c, spectrum, mask, weight, norm="paper"):
     """weight * sum_b [Re(conj X_b . 2D-IDFT^H (x_b - c_b)) + (a_inv/a_fwd)(m - 1)|X_b|^2]:
     the mask gradient of (weight/2) sum |2D-IDFT(m . X) - c|^2; c=None means x is
     already the residual x - c."""
+    _check_images(x)
+    if c is not None and (not isinstance(c, torch.Tensor) or tuple(c.shape) != tuple(x.shape)):
+        raise ValueError("c must have the shape of x %s" % (tuple(x.shape),))
+    if c is not None and c.dtype != x.dtype:
+        raise TypeError("c must have the dtype of x (%s)" % x.dtype)
+    _check_mask_tensor(mask, x.shape[-2], x.shape[-1], x.device)
     r, fin = _prep(x)
     N, M = r.shape[-2], r.shape[-1]
     batch = r.numel() // (N * M)
-    if mask.dtype != torch.float32 or tuple(mask.shape) != (N, M):
-        raise ValueError("mask must be float32 [%d, %d]" % (N, M))
     m = mask.contiguous()
     cc = None
     if c is not None:
         cc, _ = _prep(c)
     plan = get_plan(2, (N, M), batch, fin | _NORM[norm], r.device)
+    _check_spectrum(spectrum, plan, r.device)
     out = torch.empty((N, M), dtype=torch.float32, device=r.device)
     ws = plan.workspace()
     B.fft2d_filter_mse_grad(plan.h, _ptr(r), _ptr(cc), _ptr(spectrum), _ptr(m), weight, _ptr(out), _ptr(ws),
@@ -236,10 +271,16 @@ def mse_grad(x, c, spectrum, mask, weight, norm="paper"):
 def filter_mse(x, c, mask, weight, norm="paper"):
     """(loss, spectrum): loss = weight * sum |2D-IDFT(m . 2D-DFT(x)) - c|^2 (a
     0-dim float32 tensor) for float32 x, c [..., N, M], and the saved spectrum."""
+    _check_images(x)
+    if not isinstance(c, torch.Tensor) or tuple(c.shape) != tuple(x.shape):
+        raise ValueError("c must have the shape of x %s" % (tuple(x.shape),))
+    if x.dtype != torch.float32 or c.dtype != torch.float32:
+        raise TypeError("filter_mse takes float32 images")
+    _check_mask_tensor(mask, x.shape[-2], x.shape[-1], x.device)
+    if c.device != x.device:
+        raise ValueError("c is on %s, x on %s" % (c.device, x.device))
     x, fin = _prep(x)
     c, _ = _prep(c)
-    if fin != B.FFT_IN_REAL_F32:
-        raise TypeError("filter_mse takes float32 images")
     N, M = x.shape[-2], x.shape[-1]
     batch = x.numel() // (N * M)
     m = mask.contiguous()

@@ -422,6 +422,17 @@ int fft2d_spectrum(fft_plan_t p, const void* in, float* magnitude, void* workspa
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 
+int fft_plan_layout(fft_plan_t p, int* rows_per_block, int* cols_per_tile, int64_t* chunk_images,
+                    int* grad_runs) {
+  if (!plan_live(p)) return FFT_ERR_ARG;
+  if (p->kind != 2) return FFT_ERR_STATE;
+  if (rows_per_block) *rows_per_block = p->rb;
+  if (cols_per_tile) *cols_per_tile = p->w;
+  if (chunk_images) *chunk_images = p->chunk;
+  if (grad_runs) *grad_runs = p->grad_groups;
+  return FFT_OK;
+}
+
 int fft_workspace_size(fft_plan_t plan, size_t* bytes) {
   if (!plan_live(plan) || !bytes) return FFT_ERR_ARG;
   *bytes = plan->ws_bytes;
@@ -496,18 +507,22 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 
+}  // extern "C"
+
 // stages: bit 0 = row pass, bit 1 = column pass, bit 2 = inverse row pass
-static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* spectrum,
-                       void* workspace, void* stream, int stages) {
+int fftmi::filter_run(fftmi_plan* p, const void* in, void* out, const fft_mask* mask, void* spectrum,
+                      void* workspace, void* stream, int stages, int64_t chunk_images) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
   MaskArgs mk;
   int rc = fill_mask(mask, p, &mk);
   if (rc != FFT_OK) return rc;
   if (p->half) {
-    // the half-spectrum path needs H(-u, -v) = H(u, v)
-    const bool even_disc = mk.kind == FFT_MASK_DISC && (mk.c1 == 0.0 || mk.c1 == 0.5 * (double)p->n) &&
-                           (mk.c2 == 0.0 || mk.c2 == 0.5 * (double)p->m);
+    // the half-spectrum path needs H(-u, -v) = H(u, v) on the bins modulo
+    // (N, M).  The disc is evaluated on raw bin indices, so only a centre at
+    // (N/2, M/2) is even: (N - u - N/2)^2 = (u - N/2)^2 for every u, row 0
+    // included.  A centre at 0 is not (bin 1 lies inside, bin N - 1 outside).
+    const bool even_disc = mk.kind == FFT_MASK_DISC && mk.c1 == 0.5 * (double)p->n && mk.c2 == 0.5 * (double)p->m;
     if (spectrum || (mk.kind != FFT_MASK_NONE && mk.kind != FFT_MASK_GAUSSIAN && mk.kind != FFT_MASK_BUTTERWORTH &&
                      !even_disc))
       return FFT_ERR_UNSUPPORTED;
@@ -543,7 +558,7 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   const int64_t plane = p->n * p->m;
   const int64_t mc = p->half ? p->m / 2 : p->m;  // workspace columns
   const unsigned bs = (unsigned)p->bs;
-  const int64_t chunk = stages == 7 ? p->chunk : p->batch;
+  const int64_t chunk = stages == 7 ? std::max<int64_t>(1, chunk_images) : p->batch;
   for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
     const int64_t nb = std::min(chunk, p->batch - b0);
     const int64_t blocks = nb * p->n / p->rb;
@@ -574,20 +589,22 @@ static int filter_impl(fft_plan_t p, const void* in, void* out, const fft_mask* 
   return FFT_OK;
 }
 
+extern "C" {
+
 int fft2d_filter(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* workspace, void* stream) {
-  return filter_impl(p, in, out, mask, nullptr, workspace, stream, 7);
+  return filter_run(p, in, out, mask, nullptr, workspace, stream, 7, plan_live(p) ? p->chunk : 1);
 }
 
 int fft2d_filter_stage(fft_plan_t p, int stage, const void* in, void* out, const fft_mask* mask, void* workspace,
                        void* stream) {
   if (stage < 0 || stage > 2) return FFT_ERR_ARG;
-  return filter_impl(p, in, out, mask, nullptr, workspace, stream, 1 << stage);
+  return filter_run(p, in, out, mask, nullptr, workspace, stream, 1 << stage, 1);
 }
 
 int fft2d_filter_save(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* spectrum,
                       void* workspace, void* stream) {
   if (!spectrum) return FFT_ERR_ARG;
-  return filter_impl(p, in, out, mask, spectrum, workspace, stream, 7);
+  return filter_run(p, in, out, mask, spectrum, workspace, stream, 7, plan_live(p) ? p->chunk : 1);
 }
 
 // Mask gradient from a saved spectrum: in_b (the incoming gradient, or the

@@ -94,6 +94,13 @@ int grad_groups(int64_t col_tiles, int64_t batch);
 
 void destroy_ragged_state(fftmi_plan* p);
 
+// fft2d_filter's body: the passes selected by `stages` (bit 0 row pass, bit 1
+// column pass, bit 2 inverse row pass), run over the batch in chunks of
+// `chunk` images when all three are selected, with `workspace` holding one
+// chunk's blocked intermediate.
+int filter_run(fftmi_plan* p, const void* in, void* out, const fft_mask* mask, void* spectrum, void* workspace,
+               void* stream, int stages, int64_t chunk);
+
 struct MaskArgs;
 // The plan is live and its device is current (FFT_OK, FFT_ERR_ARG, FFT_ERR_STATE, FFT_ERR_HIP).
 int plan_check(const fftmi_plan* p, int* dev_out);

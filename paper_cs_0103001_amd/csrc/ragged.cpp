@@ -206,6 +206,14 @@ std::string cache_key(const fftmi_plan* p, const RaggedState* r) {
   return out;
 }
 
+// A schedule the launchers accept: a record from the cache file that is not
+// (a hand edit, another library version) is ignored, so a plan never adopts a
+// schedule that would fail at every later exec.
+bool schedule_valid(const RaggedSchedule& s) {
+  return (s.block == 128 || s.block == 256 || s.block == 512) && s.wg_cap >= 0 && s.wg_cap <= 64 &&
+         s.chunk >= 0 && s.chunk <= (int64_t(1) << 40) && (s.order == 0 || s.order == 1);
+}
+
 bool cache_lookup(const std::string& key, RaggedSchedule* s) {
   const char* path = std::getenv("FFTMI_TUNE_CACHE");
   if (!path || !*path) return false;
@@ -217,7 +225,8 @@ bool cache_lookup(const std::string& key, RaggedSchedule* s) {
     std::istringstream ls(line);
     std::string k;
     RaggedSchedule t;
-    if (ls >> k >> t.block >> t.wg_cap >> t.chunk >> t.order && k == key) {
+    std::string rest;
+    if (ls >> k >> t.block >> t.wg_cap >> t.chunk >> t.order && k == key && !(ls >> rest) && schedule_valid(t)) {
       *s = t;
       found = true;  // the last record of a key wins
     }

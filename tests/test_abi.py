@@ -106,3 +106,35 @@ def test_padded_plan_and_spectrum_argument_errors():
     p = ctypes.c_void_p(0x10)
     assert lib.fft2d_spectrum(ctypes.c_void_p(0x1234), p, p, p, None) == B.FFT_ERR_ARG
     assert lib.fft_plan_tune(ctypes.c_void_p(0x1234), p, p, None, p, None) == B.FFT_ERR_ARG
+
+
+def test_plan_layout_rejects_bad_plans():
+    lib = B.lib()
+    rb = ctypes.c_int()
+    assert lib.fft_plan_layout(None, ctypes.byref(rb), None, None, None) == B.FFT_ERR_ARG
+    assert lib.fft_plan_layout(ctypes.c_void_p(0x1234), None, None, None, None) == B.FFT_ERR_ARG
+
+
+def test_learnable_mask_wrappers_validate_before_any_launch():
+    """Shape, dtype and device mismatches raise in Python before a kernel could
+    read past a buffer (CPU tensors: the checks come before the device check)."""
+    import torch
+    from paper_cs_0103001_amd import api
+    x = torch.zeros((2, 16, 16), dtype=torch.float32)
+    mask = torch.ones((16, 16), dtype=torch.float32)
+    with pytest.raises(ValueError):
+        api.filter_mse(x, torch.zeros((1, 16, 16)), mask, 1.0)          # clean smaller than x
+    with pytest.raises(ValueError):
+        api.filter_mse(x, x, torch.ones((8, 16)), 1.0)                   # mask of another shape
+    with pytest.raises(ValueError):
+        api.filter_mse(x, x, torch.ones((16, 16), dtype=torch.float64), 1.0)
+    with pytest.raises(TypeError):
+        api.filter_mse(x.to(torch.complex64), x.to(torch.complex64), mask, 1.0)
+    with pytest.raises(ValueError):
+        api.mse_grad(x, torch.zeros((2, 16, 8)), torch.zeros(1, dtype=torch.uint8), mask, 1.0)
+    with pytest.raises(ValueError):
+        api.mse_grad(x, x, torch.zeros(1, dtype=torch.uint8), torch.ones((16, 8)), 1.0)
+    with pytest.raises(TypeError):
+        api.mse_grad(x, x.double(), torch.zeros(1, dtype=torch.uint8), mask, 1.0)
+    with pytest.raises(ValueError):
+        api.mask_grad(torch.zeros((16,), dtype=torch.complex64), torch.zeros(1, dtype=torch.uint8))

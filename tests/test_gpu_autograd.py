@@ -191,3 +191,92 @@ def test_fused_mse_finite_difference_and_input_grads():
     r = 2.0 * (y_ref - clean) / clean.size
     assert rel_l2(to_host(x.grad), oracle.filter2(r, mask).real, 2) < TOL
     assert rel_l2(to_host(c.grad), -r.real, 2) < TOL
+
+
+def _grad_runs(B, N, M, flags):
+    from paper_cs_0103001_amd import api
+    from paper_cs_0103001_amd import _binding as Bn
+    import torch
+    plan = api.get_plan(2, (N, M), B, flags, torch.device("cuda", torch.cuda.current_device()))
+    return Bn.fft_plan_layout(plan.h)["grad_runs"]
+
+
+@pytest.mark.parametrize("at_one", [True, False])
+def test_fused_mse_learn_workload_full_batch_64(at_one):
+    """The learnable workload at its own batch (64 x 1024^2): several images per
+    gradient run and the runs' partial sums added in order, against the FP64
+    oracle's loss and gradient, at mask = 1 and at a random mask."""
+    import torch
+    from paper_cs_0103001_amd import _binding as Bn
+    from paper_cs_0103001_amd.autograd import fft_filter_mse
+    B, N, M = 64, 1024, 1024
+    runs = _grad_runs(B, N, M, Bn.FFT_IN_REAL_F32)
+    per_run = -(-B // runs)
+    assert runs > 1 and per_run > 1, (runs, per_run)
+    noisy, clean = _pairs(B, N, M)
+    mask = np.ones((N, M), np.float32) if at_one else \
+        np.random.default_rng(64).uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    m = to_dev(mask).requires_grad_(True)
+    announce("fused mse B=64 1024^2 %s (runs %d x %d images)" % ("mask=1" if at_one else "random mask", runs,
+                                                                 per_run))
+    L = fft_filter_mse(to_dev(noisy), to_dev(clean), m)
+    L.backward()
+    _, L_ref, g_ref = oracle.loss_grad(noisy, clean, mask)
+    lerr = abs(float(L.detach()) - L_ref) / L_ref
+    err = rel_l2(to_host(m.grad), g_ref, 2)
+    print("learn_1024 B=64 %s: loss rel %.3e, grad relL2 %.3e" % ("mask=1" if at_one else "random", lerr, err))
+    assert lerr < 1e-5
+    assert err < TOL
+    del torch
+
+
+def test_mask_gradient_several_images_per_run():
+    """fft2d_filter_mask_grad (generic route) where a work item sums a run of
+    images and k_sum_groups adds the runs: batch 16 of 1024^2, random mask."""
+    from paper_cs_0103001_amd import _binding as Bn
+    from paper_cs_0103001_amd.autograd import fft_filter
+    B, N, M = 16, 1024, 1024
+    runs = _grad_runs(B, N, M, Bn.FFT_IN_REAL_F32)
+    assert runs > 1 and -(-B // runs) > 1, runs
+    noisy, clean = _pairs(B, N, M)
+    mask = np.random.default_rng(16).uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    m = to_dev(mask).requires_grad_(True)
+    announce("mask grad B=16 1024^2 (runs %d)" % runs)
+    y = fft_filter(to_dev(noisy), m)
+    _loss(y, to_dev(clean)).backward()
+    _, _, g_ref = oracle.loss_grad(noisy, clean, mask)
+    err = rel_l2(to_host(m.grad), g_ref, 2)
+    print("mask grad B=16 relL2 %.3e" % err)
+    assert err < TOL
+
+
+def test_mask_gradient_one_run_of_three_4096():
+    """Three 4096^2 images in one run (a single work item per column tile loops
+    over the batch), generic route, random mask."""
+    from paper_cs_0103001_amd.autograd import fft_filter
+    B, N, M = 3, 4096, 4096
+    x = np.stack([synth.image_4096(i) for i in range(B)])
+    c = (x - np.float32(1.0)).astype(np.float32)
+    mask = np.random.default_rng(4096).uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    m = to_dev(mask).requires_grad_(True)
+    announce("mask grad B=3 4096^2")
+    _loss(fft_filter(to_dev(x), m), to_dev(c)).backward()
+    _, _, g_ref = oracle.loss_grad(x, c, mask)
+    err = rel_l2(to_host(m.grad), g_ref, 2)
+    print("mask grad B=3 4096^2 relL2 %.3e" % err)
+    assert err < TOL
+
+
+def test_learnable_wrappers_reject_short_spectrum():
+    import torch
+    from paper_cs_0103001_amd import api
+    noisy, clean = _pairs(2, 64, 64)
+    x, c = to_dev(noisy), to_dev(clean)
+    m = torch.ones((64, 64), dtype=torch.float32, device="cuda")
+    _, spec = api.filter_mse(x, c, m, 1.0)
+    with pytest.raises(ValueError):
+        api.mse_grad(x, c, spec[: spec.numel() // 2], m, 1.0)
+    with pytest.raises(ValueError):
+        api.mask_grad(torch.zeros((2, 64, 64), dtype=torch.complex64, device="cuda"), spec[:16])
+    with pytest.raises(ValueError):
+        api.filter_mse(x, c, m.cpu(), 1.0)

@@ -146,3 +146,21 @@ def test_fourstep_layout_knobs(lg):
                 first = got
             else:
                 assert np.array_equal(got, first), env
+
+
+@pytest.mark.parametrize("lg", [23, 24])
+def test_longest_lengths_vs_oracle(lg):
+    """The two lengths above the measured sweep that the plan accepts (2^23:
+    2^11 x 2^12 split, 2^24: 4096-point strided columns in both passes),
+    forward and inverse against the FP64 oracle."""
+    api = _api()
+    n = 1 << lg
+    x = synth.uniform_complex((2, n), (13, lg))
+    announce("fft1d n=2^%d batch=2" % lg)
+    X = to_host(api.fft(to_dev(x)))
+    ef = rel_l2(X, oracle.fft(x, threads=8), 1)
+    announce("ifft1d n=2^%d batch=2" % lg)
+    f = to_host(api.ifft(to_dev(x)))
+    ei = rel_l2(f, oracle.ifft(x, threads=8), 1)
+    print("2^%d forward relL2 %.3e inverse %.3e" % (lg, ef, ei))
+    assert ef < TOL and ei < TOL

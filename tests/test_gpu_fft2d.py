@@ -147,3 +147,57 @@ def test_filter_in_place_and_deterministic():
     a = to_host(api.fft2d_filter(x, spec))
     b = to_host(api.fft2d_filter(x, spec))
     np.testing.assert_array_equal(a, b)
+
+
+def test_largest_plane_16384_separable():
+    """16384 x 16384, the largest rank-2 plan (its blocked workspace, 2.15 GB,
+    is above 2^31 bytes).  A separable image f = g h^T (integers, so every
+    product is exact in float32) filtered by the separable Gaussian mask gives
+    y = a b^T with a, b the 1D filters of g and h (eq. 5 and the 2D-IDFT
+    factor into row and column sums); a, b come from the FP64 oracle's 1D
+    transforms and masks.  Every element is compared."""
+    import torch
+    from paper_cs_0103001_amd import api
+    N = M = 16384
+    rng = np.random.default_rng(16384)
+    g = rng.integers(-2048, 2049, N).astype(np.float64)
+    h = rng.integers(-2048, 2049, M).astype(np.float64)
+    sig = 0.05
+    gu = oracle.mask_gaussian(N, 1, sig)[:, 0]
+    gv = oracle.mask_gaussian(1, M, sig)[0]
+    a = oracle.ifft(gu * oracle.fft(g, threads=8), threads=8)
+    b = oracle.ifft(gv * oracle.fft(h, threads=8), threads=8)
+    x = torch.from_numpy(g.astype(np.float32)).cuda()[:, None] * torch.from_numpy(h.astype(np.float32)).cuda()[None, :]
+    announce("filter 16384^2 separable")
+    y = api.fft2d_filter(x, dict(kind="gaussian", sigma_f=sig))
+    torch.cuda.synchronize()
+    del x
+    num = den = 0.0
+    for r0 in range(0, N, 1024):
+        got = y[r0:r0 + 1024].cpu().numpy().astype(np.complex128)
+        ref = np.outer(a[r0:r0 + 1024], b)
+        num += float(np.sum(np.abs(got - ref) ** 2))
+        den += float(np.sum(np.abs(ref) ** 2))
+    err = (num / den) ** 0.5
+    print("16384^2 separable filter relL2 %.3e" % err)
+    assert err < TOL
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+def test_non_finite_input_propagates(bad):
+    """A NaN or Inf pixel spreads through the transforms (every bin of its
+    image's spectrum takes it) without an error status or a fault; the other
+    images of the batch stay finite and equal to their oracle results."""
+    from paper_cs_0103001_amd import api
+    N = M = 256
+    x = np.stack([synth.star_field(N, M, 50, 1.5, (97, b)) for b in range(3)])
+    x[1, 17, 33] = bad
+    announce("non-finite input %s" % bad)
+    y = to_host(api.fft2d_filter(to_dev(x), dict(kind="butterworth", cutoff=0.15, order=4)))
+    assert not np.isfinite(y[1]).any()
+    m = oracle.mask_butterworth(N, M, 0.15, 4)
+    for b in (0, 2):
+        assert np.isfinite(y[b]).all()
+        assert rel_l2(y[b], oracle.filter2(x[b], m), 2) < TOL
+    yr = to_host(api.fft2d_filter(to_dev(x), None, real_even=True, real_output=True))
+    assert not np.isfinite(yr[1]).any() and np.isfinite(yr[0]).all() and np.isfinite(yr[2]).all()

@@ -60,3 +60,18 @@ def test_half_spectrum_rejects_odd_masks():
         api.fft2d_filter(x, torch.ones((64, 64), device="cuda"), real_even=True)
     with pytest.raises(B.FFTError):
         api.fft2d_filter(x, dict(kind="disc", b=10.0, c1=5.0, c2=7.0), real_even=True)
+    # a disc centred at bin 0 is not even on the raw bin grid: bin (1, 1) lies
+    # inside, bin (63, 63) outside, so the half spectrum would be wrong
+    for c1, c2 in ((0.0, 0.0), (32.0, 0.0), (0.0, 32.0)):
+        with pytest.raises(B.FFTError):
+            api.fft2d_filter(x, dict(kind="disc", b=10.0, c1=c1, c2=c2), real_even=True)
+
+
+def test_disc_centred_at_zero_full_path_vs_oracle():
+    """The same disc on the full path (which has no evenness requirement)."""
+    from paper_cs_0103001_amd import api
+    N = M = 64
+    x = synth.star_field(N, M, 20, 1.5, (95, N))
+    announce("disc at 0, full path")
+    y = to_host(api.fft2d_filter(to_dev(x), dict(kind="disc", b=10.0, c1=0.0, c2=0.0)))
+    assert rel_l2(y, oracle.filter2(x, oracle.mask_disc(N, M, 10.0, 0.0, 0.0)), 2) < TOL

@@ -198,3 +198,35 @@ def test_misaligned_workspace_rejected():
     pr = api.get_plan(0, (), len(sizes), B.FFT_IN_REAL_F32, dev, ragged_sizes=sizes)
     wsr = torch.empty(pr.workspace_bytes + 64, dtype=torch.uint8, device=dev)
     refused(lambda w: B.fft2d_filter_ragged(pr.h, api._ptr(xr), api._ptr(orr), mk, w, st), wsr)
+
+
+def test_tune_cache_records_are_validated(tmp_path, monkeypatch):
+    """A schedule the launchers would refuse is ignored at plan creation (the
+    plan keeps the default schedule and runs); a valid record is adopted."""
+    from paper_cs_0103001_amd import api
+    from paper_cs_0103001_amd import _binding as B
+    sizes = [256, 64, 128, 64]
+    imgs, flat = _images(sizes, seed0=700)
+    x = to_dev(flat)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("FFTMI_TUNE_CACHE", str(cache))
+    mask = dict(kind="gaussian", sigma_f=SIGMA_F)
+    announce("tune cache validation")
+    api.tune_ragged(x, sizes, mask)
+    key = cache.read_text().split()[0]
+    default = {"block": 256, "wg_cap": 0, "chunk_bytes": 0, "order": 0}
+    for bad in ("7 0 0 0", "256 -1 0 0", "256 0 -5 0", "256 0 0 9", "512 0 0 0 extra", "256 0"):
+        cache.write_text("%s %s\n" % (key, bad))
+        h = B.fft_plan_ragged(sizes, B.FFT_IN_REAL_F32)
+        try:
+            assert B.fft_plan_schedule(h) == default, bad
+        finally:
+            B.fft_plan_destroy(h)
+    cache.write_text("%s 512 2 0 1\n" % key)
+    h = B.fft_plan_ragged(sizes, B.FFT_IN_REAL_F32)
+    try:
+        assert B.fft_plan_schedule(h) == {"block": 512, "wg_cap": 2, "chunk_bytes": 0, "order": 1}
+    finally:
+        B.fft_plan_destroy(h)
+    monkeypatch.delenv("FFTMI_TUNE_CACHE")
+    _check(to_host(api.filter_ragged(x, sizes, mask)), imgs, sizes)
