@@ -51,6 +51,7 @@ extern "C" {
 #define FFT_ERR_HIP (-5)         /* a HIP runtime call failed (text via fft_strerror) */
 #define FFT_ERR_NOMEM (-6)       /* host or device allocation failed */
 #define FFT_ERR_STATE (-7)       /* plan used on another device, or wrong plan kind */
+#define FFT_ERR_SCRATCH (-8)     /* fft2d_filter_noalloc: the plan needs more than its static scratch */
 
 /* ------------------------------------------------------------- directions */
 #define FFT_FORWARD (-1)     /* eq. E2 (1D) / eq. 5 (2D) */
@@ -262,6 +263,26 @@ int fft_plan_schedule(fft_plan_t plan, int* block, int* wg_cap, int64_t* chunk_b
  * kinds. */
 int fft_plan_layout(fft_plan_t plan, int* rows_per_block, int* cols_per_tile, int64_t* chunk_images,
                     int* grad_runs);
+
+/* fft2d_filter for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result as fft2d_filter, but the intermediate lives in a
+ * library-owned static device array of FFT_NOALLOC_SCRATCH_BYTES per device
+ * (held from library load until the process ends) instead of a caller
+ * workspace.  The call allocates no device memory (the plan's twiddle
+ * tables were made by fft_plan); its first call on a device also records
+ * the array's address and the kernels' occupancy in host-side caches, and
+ * later calls allocate nothing at all.  The caller still passes in and out
+ * (as fft2d_filter, in may equal out).  A plan whose filter needs more than
+ * the array (one chunk's blocked intermediate: up to a 4096 x 4096 image, or
+ * a batch chunk of 128 MiB; a padded plan's whole workspace) returns
+ * FFT_ERR_SCRATCH before any device work.  Every call on one device shares
+ * that device's array and leaves the last call's contents in it: calls that
+ * overlap on one device (other streams, other threads) race and must be
+ * serialised by the caller.  Nothing in the array needs to start at zero.
+ * Other errors as fft2d_filter. */
+#define FFT_NOALLOC_SCRATCH_BYTES ((size_t)144 << 20)
+int fft2d_filter_noalloc(fft_plan_t plan, const void* in, void* out, const fft_mask* mask, void* stream);
 
 /* Release a plan (and any graph it instantiated).  NULL is a no-op. */
 int fft_plan_destroy(fft_plan_t plan);

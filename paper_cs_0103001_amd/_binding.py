@@ -17,6 +17,8 @@ FFT_ERR_WORKSPACE = -4
 FFT_ERR_HIP = -5
 FFT_ERR_NOMEM = -6
 FFT_ERR_STATE = -7
+FFT_ERR_SCRATCH = -8
+FFT_NOALLOC_SCRATCH_BYTES = 144 << 20
 
 FFT_FORWARD = -1
 FFT_INVERSE = 1
@@ -62,6 +64,7 @@ _SIGS = {
     "fft_spectrum_size": (ctypes.c_int, [_P, _SIZEP]),
     "fft_exec": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P]),
     "fft2d_filter": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
+    "fft2d_filter_noalloc": (ctypes.c_int, [_P, _P, _P, _MASKP, _P]),
     "fft2d_filter_stage": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _MASKP, _P, _P]),
     "fft2d_filter_save": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P, _P]),
     "fft2d_filter_mask_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -161,6 +164,11 @@ def fft_exec(plan, inp, out, workspace, direction, stream):
 def fft2d_filter(plan, inp, out, mask, workspace, stream):
     check(lib().fft2d_filter(plan, inp, out, ctypes.byref(mask) if mask is not None else None, workspace,
                              stream), "fft2d_filter")
+
+
+def fft2d_filter_noalloc(plan, inp, out, mask, stream):
+    check(lib().fft2d_filter_noalloc(plan, inp, out, ctypes.byref(mask) if mask is not None else None, stream),
+          "fft2d_filter_noalloc")
 
 
 def fft2d_filter_stage(plan, stage, inp, out, mask, workspace, stream):

@@ -268,6 +268,8 @@ const char* fft_strerror(int code) {
       return "out of memory";
     case FFT_ERR_STATE:
       return "plan used on another device or with the wrong entry point";
+    case FFT_ERR_SCRATCH:
+      return "the plan needs more than the static scratch of fft2d_filter_noalloc";
     default:
       return "unknown status";
   }

@@ -24,7 +24,7 @@ def test_library_exports_header_functions():
 
 def test_strerror_texts():
     for code in (B.FFT_OK, B.FFT_ERR_ARG, B.FFT_ERR_SIZE, B.FFT_ERR_UNSUPPORTED, B.FFT_ERR_WORKSPACE,
-                 B.FFT_ERR_HIP, B.FFT_ERR_NOMEM, B.FFT_ERR_STATE, -99):
+                 B.FFT_ERR_HIP, B.FFT_ERR_NOMEM, B.FFT_ERR_STATE, B.FFT_ERR_SCRATCH, -99):
         assert isinstance(B.strerror(code), str) and B.strerror(code)
 
 
@@ -76,6 +76,7 @@ def test_calls_reject_bad_plans():
     p = ctypes.c_void_p(0x10)
     assert lib.fft_exec(bogus, p, p, p, B.FFT_FORWARD, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter(bogus, p, p, None, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_noalloc(bogus, p, p, None, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_save(bogus, p, p, None, p, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_mask_grad(bogus, p, p, p, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_mse_grad(bogus, p, p, p, p, 1.0, p, p, None) == B.FFT_ERR_ARG
