@@ -235,7 +235,10 @@ int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32
  * and the 2D-IDFT with each image's own N = M = side): one persistent launch
  * per pass covering all sides, the launches of a call captured in a HIP graph
  * that later calls with the same buffers and mask replay (a call with other
- * buffers captures again).  Masks: FFT_MASK_NONE, GAUSSIAN, BUTTERWORTH (in
+ * buffers captures again).  Images of sides up to the schedule's single-pass
+ * limit (128 by default) are filtered whole in LDS by one more persistent
+ * launch (read once, written once), which the graph runs as a branch beside
+ * the three passes of the larger images.  Masks: FFT_MASK_NONE, GAUSSIAN, BUTTERWORTH (in
  * cycles per pixel, so one mask serves every side); TENSOR and DISC return
  * FFT_ERR_UNSUPPORTED.  Other errors as fft2d_filter. */
 int fft2d_filter_ragged(fft_plan_t plan, const void* in_packed, void* out_packed, const fft_mask* mask,
@@ -244,15 +247,20 @@ int fft2d_filter_ragged(fft_plan_t plan, const void* in_packed, void* out_packed
 /* Autotune a ragged plan's launch schedule on the caller's buffers (which it
  * overwrites), blocking until done: every candidate (threads per workgroup
  * 256 or 512, resident workgroups per CU as many as fit or 2, passes over the
- * whole batch or over runs of images of at most 128 MiB of intermediate) is
+ * whole batch or over runs of images of at most 128 MiB of intermediate, and
+ * the largest side filtered in one pass from LDS: none, 64 or 128) is
  * run once to warm up and timed over three calls with HIP events on `stream`;
  * the fastest stays with the plan and, when FFTMI_TUNE_CACHE is set, is
  * appended to that file.  FFT_ERR_UNSUPPORTED for other plan kinds. */
 int fft_plan_tune(fft_plan_t plan, const void* in_packed, void* out_packed, const fft_mask* mask, void* workspace,
                   void* stream);
 
-/* The schedule a ragged plan uses (any pointer may be NULL). */
-int fft_plan_schedule(fft_plan_t plan, int* block, int* wg_cap, int64_t* chunk_bytes, int* order);
+/* The schedule a ragged plan uses (any pointer may be NULL): threads per
+ * workgroup, resident workgroups per CU (0: as many as fit), bytes of
+ * intermediate per run of images (0: one run), tile order (0: largest images
+ * first), and the largest side whose images run in one pass from LDS (0:
+ * none; at most 128). */
+int fft_plan_schedule(fft_plan_t plan, int* block, int* wg_cap, int64_t* chunk_bytes, int* order, int* small_side);
 
 /* Layout of a rank-2 plan (any pointer may be NULL), for callers that check
  * which kernel path a batch takes: rows per block of the blocked workspace
@@ -283,6 +291,57 @@ int fft_plan_layout(fft_plan_t plan, int* rows_per_block, int* cols_per_tile, in
  * Other errors as fft2d_filter. */
 #define FFT_NOALLOC_SCRATCH_BYTES ((size_t)144 << 20)
 int fft2d_filter_noalloc(fft_plan_t plan, const void* in, void* out, const fft_mask* mask, void* stream);
+
+/* ------------------------------------------------ the parallel tree (Section 2)
+ * Section 2's construction of the FFT by 2^l processes, emulated on one GPU
+ * with one workgroup per process.  With N = 2^m data and m1 = m - l:
+ *   - process p (0 <= p < 2^l; p = 0 is the master) takes the branch of the
+ *     data C(j) with j = p mod 2^l, in the tree's bit-reversed leaf order, and
+ *     builds the polynomials of levels 1 .. m1 of that branch alone;
+ *   - at level m1 + i (i = 1 .. l) the processes p' = p + 2^(l-i) send their
+ *     level-(m1+i-1) vectors to p (a message through device memory: the
+ *     sender writes its vector to its level's mailbox and releases a flag, the receiver
+ *     acquires it and unpacks the vector next to its own), and each receiver
+ *     p < 2^(l-i) merges the two;
+ *   - the master's P_0^(m) is the DFT; out = P_0^(m) times eq. (E2)'s 1/N
+ *     (FFT_NORM_PAPER) or unscaled (FFT_NORM_NUMPY), complex64.
+ * Each process counts the products it generates as Section 4 does (one per
+ * coefficient of each polynomial it builds: (m - l) 2^(m-l) for every
+ * process in the branch phase, then 2^(m-l+i) at level m1 + i for the
+ * receivers), so the master's count is eq. (multi), the critical path of
+ * Table 1, and the counts of all processes add up to N log2 N. */
+#define FFT_TREE_MAX_LOG2_PROCS 6 /* at most 64 processes, all resident at once */
+#define FFT_TREE_MAX_LOG2 20      /* N <= 2^20 */
+typedef struct fft_tree_stats {
+  int64_t products[1 << FFT_TREE_MAX_LOG2_PROCS];   /* products generated by each process */
+  int64_t busy_ticks[1 << FFT_TREE_MAX_LOG2_PROCS]; /* time computing, device wall clock (100 MHz) ticks */
+  int64_t wait_ticks[1 << FFT_TREE_MAX_LOG2_PROCS]; /* time waiting for a message, same ticks */
+  int64_t sent_to[1 << FFT_TREE_MAX_LOG2_PROCS];    /* receiver of the process's vector; -1 for the master */
+  int64_t send_level[1 << FFT_TREE_MAX_LOG2_PROCS]; /* tree level of the vector it sent; -1 for the master */
+  int64_t status;                                   /* 0; 1 if a receiver gave up waiting (spin_limit) */
+} fft_tree_stats;
+
+/* Plan the tree for N = n data (a power of two, 2^log2_procs <= n <= 2^20)
+ * and 2^log2_procs processes (0 .. 6, and no more than the device has
+ * compute units).  flags: FFT_NORM_PAPER or FFT_NORM_NUMPY.  The plan holds
+ * Table 2's factors Z[j] = e^{-2 pi i j/N} (j < N/2, from the exact integer j
+ * in FP64, rounded once to float).  fft_workspace_size gives
+ * (1 + log2_procs) * n * 8 + 256 bytes: the tree array [n] (complex64,
+ * bit-reversed leaf order), then one mailbox [n] per merge level m1 + i
+ * (i = 1 .. log2_procs; each sender's vector at its own position in the tree
+ * array, left there after the call), then one flag per process.
+ * Errors: FFT_ERR_ARG, FFT_ERR_SIZE, FFT_ERR_UNSUPPORTED (more processes than
+ * compute units), FFT_ERR_NOMEM, FFT_ERR_HIP. */
+int fft_plan_tree(fft_plan_t* out, int64_t n, int log2_procs, uint32_t flags);
+
+/* Run the emulation on one signal: in, out complex64 [n] (device, distinct);
+ * stats a device fft_tree_stats, overwritten; a receiver polls its partner's
+ * flag at most spin_limit (>= 1) times, about 0.1 us apart, before it gives up
+ * and sets stats->status = 1 (then out is not valid).  Errors: FFT_ERR_ARG,
+ * FFT_ERR_STATE (not a tree plan, other device), FFT_ERR_WORKSPACE,
+ * FFT_ERR_HIP. */
+int fft_tree_exec(fft_plan_t plan, const void* in, void* out, void* workspace, fft_tree_stats* stats,
+                  int64_t spin_limit, void* stream);
 
 /* Release a plan (and any graph it instantiated).  NULL is a no-op. */
 int fft_plan_destroy(fft_plan_t plan);

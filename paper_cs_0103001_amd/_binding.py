@@ -74,11 +74,13 @@ _SIGS = {
     "fft2d_filter_ragged": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
     "fft_plan_tune": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
     "fft_plan_schedule": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                         _I64P, ctypes.POINTER(ctypes.c_int)]),
+                                         _I64P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "fft_plan_padded": (ctypes.c_int, [ctypes.POINTER(_P), _I64P, ctypes.c_int64, ctypes.c_uint32]),
     "fft2d_spectrum": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "fft_plan_layout": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _I64P,
                                        ctypes.POINTER(ctypes.c_int)]),
+    "fft_plan_tree": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int64, ctypes.c_int, ctypes.c_uint32]),
+    "fft_tree_exec": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int64, _P]),
     "fft_plan_destroy": (ctypes.c_int, [_P]),
     "fft_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "fft_version": (ctypes.c_int, []),
@@ -207,11 +209,11 @@ def fft_plan_tune(plan, inp, out, mask, workspace, stream):
 
 
 def fft_plan_schedule(plan):
-    b, c, o = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    b, c, o, sm = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
     ch = ctypes.c_int64()
-    check(lib().fft_plan_schedule(plan, ctypes.byref(b), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(o)),
-          "fft_plan_schedule")
-    return {"block": b.value, "wg_cap": c.value, "chunk_bytes": ch.value, "order": o.value}
+    check(lib().fft_plan_schedule(plan, ctypes.byref(b), ctypes.byref(c), ctypes.byref(ch), ctypes.byref(o),
+                                  ctypes.byref(sm)), "fft_plan_schedule")
+    return {"block": b.value, "wg_cap": c.value, "chunk_bytes": ch.value, "order": o.value, "small_side": sm.value}
 
 
 def fft_plan_layout(plan):
@@ -220,6 +222,30 @@ def fft_plan_layout(plan):
     check(lib().fft_plan_layout(plan, ctypes.byref(rb), ctypes.byref(w), ctypes.byref(ch), ctypes.byref(g)),
           "fft_plan_layout")
     return {"rows_per_block": rb.value, "cols_per_tile": w.value, "chunk_images": ch.value, "grad_runs": g.value}
+
+
+FFT_TREE_MAX_LOG2_PROCS = 6
+FFT_TREE_MAX_LOG2 = 20
+TREE_STATS_FIELDS = ("products", "busy_ticks", "wait_ticks", "sent_to", "send_level")
+TREE_STATS_INT64 = len(TREE_STATS_FIELDS) * (1 << FFT_TREE_MAX_LOG2_PROCS) + 1  # + status
+
+
+def fft_plan_tree(n, log2_procs, flags=0):
+    h = _P()
+    check(lib().fft_plan_tree(ctypes.byref(h), int(n), int(log2_procs), int(flags)), "fft_plan_tree")
+    return h
+
+
+def fft_tree_exec(plan, inp, out, workspace, stats, spin_limit, stream):
+    check(lib().fft_tree_exec(plan, inp, out, workspace, stats, int(spin_limit), stream), "fft_tree_exec")
+
+
+def tree_stats_dict(raw, nproc):
+    """fft_tree_stats read back as int64 values -> dict of per-process lists."""
+    P = 1 << FFT_TREE_MAX_LOG2_PROCS
+    out = {f: [int(v) for v in raw[i * P:i * P + nproc]] for i, f in enumerate(TREE_STATS_FIELDS)}
+    out["status"] = int(raw[len(TREE_STATS_FIELDS) * P])
+    return out
 
 
 def fft_plan_destroy(plan):

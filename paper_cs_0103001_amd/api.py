@@ -324,3 +324,54 @@ def tune_ragged(packed, sizes, mask, real_output=False):
     ws = plan.workspace()
     B.fft_plan_tune(plan.h, _ptr(x), _ptr(out), mk, _ptr(ws), _stream(x.device))
     return B.fft_plan_schedule(plan.h)
+
+
+class TreePlan:
+    """Owns one tree plan (fft_plan_tree) on a device."""
+
+    def __init__(self, n, log2_procs, flags, device):
+        self.device = device
+        with torch.cuda.device(device):
+            self.h = B.fft_plan_tree(n, log2_procs, flags)
+        self.n, self.log2_procs = n, log2_procs
+        self.workspace_bytes = B.fft_workspace_size(self.h)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and B is not None and getattr(B, "_lib", None) is not None:
+            try:
+                B.fft_plan_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+
+_tree_cache = {}
+
+
+def tree_fft(x, log2_procs, norm="paper", spin_limit=1 << 24):
+    """Section 2's parallel tree on 2^log2_procs processes, emulated with one
+    workgroup per process, on one complex64 signal x [n].  Returns
+    (out, stats, mailbox): the transform (eq. E2's 1/N under norm="paper"),
+    the per-process statistics (products generated, busy and waiting device
+    ticks, receiver and level of each send, status), and the mailboxes
+    [log2_procs][n], row i - 1 holding the vectors sent at merge level m1 + i,
+    each at its place in the bit-reversed tree array."""
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.complex64 or x.dim() != 1:
+        raise TypeError("expected a 1-D complex64 CUDA (HIP) tensor")
+    x = x.contiguous()
+    n = x.numel()
+    key = (n, int(log2_procs), _NORM[norm], x.device.index)
+    with _cache_lock:
+        p = _tree_cache.get(key)
+        if p is None:
+            p = TreePlan(n, int(log2_procs), _NORM[norm], x.device)
+            _tree_cache[key] = p
+    out = torch.empty_like(x)
+    ws = torch.empty(p.workspace_bytes, dtype=torch.uint8, device=x.device)
+    stats = torch.empty(B.TREE_STATS_INT64, dtype=torch.int64, device=x.device)
+    B.fft_tree_exec(p.h, _ptr(x), _ptr(out), _ptr(ws), _ptr(stats), int(spin_limit), _stream(x.device))
+    nproc = 1 << int(log2_procs)
+    st = B.tree_stats_dict(stats.cpu().tolist(), nproc)
+    mailbox = ws[n * 8:(1 + int(log2_procs)) * n * 8].view(torch.complex64).view(int(log2_procs), n)
+    return out, st, mailbox

@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfftmi.so")
 ARCH = os.environ.get("FFTMI_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "ragged_kernels.hip", "api.cpp", "tune.cpp", "ragged.cpp", "noalloc.hip"]
+SOURCES = ["kernels.hip", "ragged_kernels.hip", "api.cpp", "tune.cpp", "ragged.cpp", "noalloc.hip", "tree.hip"]
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 

@@ -314,8 +314,17 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
         const int v = std::atoi(e);
         if (v >= 1 && v <= 16 && (v & (v - 1)) == 0) wmax = v;
       }
-      p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, wmax);
-      p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, wmax);
+      // threads per tile of each pass (512, or 1024 for twice the columns
+      // per tile without the prefetch)
+      auto fs_threads = [](const char* name, int dflt) {
+        if (const char* e = std::getenv(name)) {
+          const int v = std::atoi(e);
+          if (v == 512 || v == 1024) return v;
+        }
+        return dflt;
+      };
+      p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, wmax, fs_threads("FFTMI_FS_THREADS1", 512));
+      p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, wmax, fs_threads("FFTMI_FS_THREADS2", 512));
       rc = fourstep_tables(t, p->log_n, p->log_n1, &p->tw_fs);
       if (rc != FFT_OK) return rc;
       // the intermediate [N2][N1] rows get a padded stride, so that the
@@ -722,6 +731,7 @@ int fft_plan_destroy(fft_plan_t p) {
   plan_unregister(p);
   p->magic = 0;
   destroy_ragged_state(p);
+  destroy_tree_state(p);
   delete p;
   return FFT_OK;
 }

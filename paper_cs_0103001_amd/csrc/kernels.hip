@@ -838,16 +838,17 @@ __global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ p
 // ============================================================== kernel E
 // Strided column pass over an [L][C] matrix per batch entry (the four-step
 // long 1D transform): row r of entry b starts at b*ib + r*irs.
-// twiddle_transpose: pass one (store transposed, column c as the row of L
+// TT: pass one (store transposed, column c as the row of L
 // entries at b*ob + c*ors, each entry times W_N^{k1 n2} = tfs[n2*L + k1],
 // read in the same order as the stores); otherwise pass two (store [L][C]
 // with row stride ors).
-template <int L, bool INV>
-__global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __restrict__ in, float2* __restrict__ out,
-                                                       int C, int w, int ltiles, int ntiles, int twiddle_transpose,
-                                                       float scale, const float2* __restrict__ tfs,
-                                                       const float2* __restrict__ tws, int64_t ib, int irs,
-                                                       int64_t ob, int ors) {
+// WIDE: tiles of up to 1024 threads (twice the columns of the 512-thread
+// tiles, so twice the contiguous bytes per row), with no prefetch, as the
+// 128 VGPRs a thread then has leave no room for a second tile.
+template <int L, bool INV, bool WIDE, bool TT>
+__global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
+    const float2* __restrict__ in, float2* __restrict__ out, int C, int w, int ltiles, int ntiles, float scale,
+    const float2* __restrict__ tfs, const float2* __restrict__ tws, int64_t ib, int irs, int64_t ob, int ors) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const int lw = ilog2_pow2(w);
@@ -860,7 +861,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
   const unsigned qs = (unsigned)(TPT * irs);
   const unsigned lane = (unsigned)(j * irs + c);
   const int tmask = (1 << ltiles) - 1;
-  constexpr bool PF = TPT <= 512;  // 1024-thread transforms have no room for a second tile
+  constexpr bool PF = TPT <= 512 && !WIDE;  // 1024-thread workgroups have no room for a second tile
   float2 a[E], nx[PF ? E : 1];
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
     const float2* b = in + (int64_t)(t >> ltiles) * ib + (t & tmask) * w;
@@ -885,7 +886,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_strided(const float2* __r
     const int64_t bo = (int64_t)(t >> ltiles) * ob;
     const int c0 = (t & tmask) * w;
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
-    if (twiddle_transpose) {
+    if constexpr (TT) {
       // transposed store through LDS: out[n2][k1], contiguous along k1
       const int nthr = w * TPT;
       const int lL = ilog2_pow2(L);
@@ -1237,19 +1238,41 @@ struct ColsGrad {
 
 template <int LG>
 struct ColsStrided {
+  template <bool INV, bool WIDE, bool TT>
+  static hipError_t go_one(const float2* in, float2* out, int64_t ntiles, int w, int lds, int C, int lt, float scale,
+                           const float2* tfs, const float2* tw, int64_t ib, int irs, int64_t ob, int ors,
+                           const Launch& lc) {
+    constexpr int TPT = threads_per_transform(1 << LG);
+    return go(k_cols_strided<1 << LG, INV, WIDE, TT>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt,
+              (int)ntiles, scale, tfs, tw, ib, irs, ob, ors);
+  }
+  template <bool INV, bool WIDE>
+  static hipError_t go_tt(bool twt, const float2* in, float2* out, int64_t ntiles, int w, int lds, int C, int lt,
+                          float scale, const float2* tfs, const float2* tw, int64_t ib, int irs, int64_t ob, int ors,
+                          const Launch& lc) {
+    return twt ? go_one<INV, WIDE, true>(in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc)
+               : go_one<INV, WIDE, false>(in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc);
+  }
   static hipError_t run(bool inv, bool twt, const float2* in, float2* out, int64_t batch, int C, int w, float scale,
                         const float2* tfs, int64_t ib, int irs, int64_t ob, int ors, const Launch& lc) {
-    constexpr int L = 1 << LG, TPT = threads_per_transform(L);
-    const int tiles = C / w;
-    const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
-    const float2* tw = twiddle_src<L>(lc);
-    const int64_t ntiles = batch * tiles;
-    const int lt = ilog2c(tiles);
-    if (inv)
-      return go(k_cols_strided<L, true>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
-                scale, tfs, tw, ib, irs, ob, ors);
-    return go(k_cols_strided<L, false>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt, (int)ntiles, (int)twt,
-              scale, tfs, tw, ib, irs, ob, ors);
+    // the four-step splits use column lengths 2^7 .. 2^12 only
+    if constexpr (LG < 7 || LG > 12) {
+      return hipErrorInvalidValue;
+    } else {
+      constexpr int L = 1 << LG, TPT = threads_per_transform(L);
+      const int tiles = C / w;
+      const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
+      const float2* tw = twiddle_src<L>(lc);
+      const int64_t ntiles = batch * tiles;
+      const int lt = ilog2c(tiles);
+      if (w * TPT > 1024) return hipErrorInvalidValue;
+      const bool wide = w * TPT > max_block<L>();
+      if (inv)
+        return wide ? go_tt<true, true>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc)
+                    : go_tt<true, false>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc);
+      return wide ? go_tt<false, true>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc)
+                  : go_tt<false, false>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc);
+    }
   }
 };
 

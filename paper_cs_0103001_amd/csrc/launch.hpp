@@ -172,6 +172,18 @@ hipError_t launch_ragged_pass(int pass, const void* in, bool in_f32, float2* ws,
                               const RaggedImage* imgs, const int2* tiles, int ntiles, int block, int grid,
                               const MaskArgs& mk, const TwTable& tw, bool numpy, hipStream_t st);
 
+// Small images: sides up to 2^kRaggedSmallMaxLog2 can run in one pass from
+// LDS (k_ragged_small), ragged_small_ipw(lg) images of side 2^lg per work
+// item {first entry of idx, count}; the workgroups have kRaggedSmallBlock
+// threads.
+constexpr int kRaggedSmallMaxLog2 = 7;
+constexpr int kRaggedSmallBlock = 1024;
+int ragged_small_ipw(int lg);
+hipError_t ragged_small_grid(bool in_f32, bool out_f32, int mask_kind, int nitems, int* grid);
+hipError_t launch_ragged_small(const void* in, bool in_f32, void* out, bool out_f32, const RaggedImage* imgs,
+                               const int* idx, const int2* items, int nitems, int grid, const MaskArgs& mk,
+                               const TwTable& tw, bool numpy, hipStream_t st);
+
 // LDS bytes of one launch configuration (for the host's occupancy checks).
 int lds_bytes_rows_rm(int log2L, int tpw);
 int lds_bytes_cols(int log2L, int w);

@@ -59,6 +59,9 @@ struct fftmi_plan {
   int grad_groups = 1;
   size_t part_off = 0, loss_off = 0, loss_mid_off = 0;
   fftmi::RaggedState* ragged = nullptr;
+  // fft_plan_tree: log2 of the number of processes, Table 2's factors Z[0 .. N/2)
+  int tree_l = 0;
+  const float2* tree_z = nullptr;
 };
 
 namespace fftmi {
@@ -76,8 +79,9 @@ int64_t block_pad(int64_t stride);
 // Pad (elements) of the four-step intermediate's rows of 2^log_n1 entries.
 int fourstep_pad(int log_n1);
 
-// Widest power-of-two column tile (<= wmax, <= cols) that fits one workgroup.
-int widest_cols_tile(int log2L, int cols, int wmax);
+// Widest power-of-two column tile (<= wmax, <= cols) that fits one workgroup
+// of at most max_threads threads (0: the kernel's usual limit) and the LDS.
+int widest_cols_tile(int log2L, int cols, int wmax, int max_threads = 0);
 
 // Column tile width for a rank-2 plan (autotuned value if one is cached).
 int tuned_cols_width(const fftmi_plan* p, int cols);
@@ -93,6 +97,7 @@ int64_t filter_chunk(int64_t N, int64_t M, int64_t batch);
 int grad_groups(int64_t col_tiles, int64_t batch);
 
 void destroy_ragged_state(fftmi_plan* p);
+void destroy_tree_state(fftmi_plan* p);
 
 // fft2d_filter's body: the passes selected by `stages` (bit 0 row pass, bit 1
 // column pass, bit 2 inverse row pass), run over the batch in chunks of

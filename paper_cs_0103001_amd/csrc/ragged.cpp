@@ -13,6 +13,9 @@
 //           in the memory-side cache between passes), and the workspace
 //           region is reused by every run
 //   order   0: tiles of the largest images first; 1: the images' own order
+//   small   images of side <= 2^small run in one pass from LDS (one launch
+//           of their own, beside the three passes of the larger images);
+//           -1: every image takes the three passes
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -40,6 +43,7 @@ struct RaggedSchedule {
   int wg_cap = 0;
   int64_t chunk = 0;
   int order = 0;
+  int small = kRaggedSmallMaxLog2;
 };
 
 struct RaggedRun {  // one run of images: the tile range of each pass
@@ -55,6 +59,15 @@ struct RaggedState {
   std::vector<RaggedRun> runs;
   RaggedImage* d_imgs = nullptr;
   int2* d_tiles[3] = {nullptr, nullptr, nullptr};
+  // images of the single-pass LDS path: their indices (largest side first)
+  // and the work items {first entry, count}
+  int* d_small_idx = nullptr;
+  int2* d_small_items = nullptr;
+  int n_small_items = 0;
+  // the small images' launch runs on a second stream, forked from and
+  // joined to the caller's stream (a parallel branch of the captured graph)
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   TwTable tw{};
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
@@ -88,9 +101,16 @@ void free_lists(RaggedState* r) {
   if (r->d_imgs) (void)hipFree(r->d_imgs);
   for (auto& t : r->d_tiles)
     if (t) (void)hipFree(t);
+  if (r->d_small_idx) (void)hipFree(r->d_small_idx);
+  if (r->d_small_items) (void)hipFree(r->d_small_items);
   r->d_imgs = nullptr;
   r->d_tiles[0] = r->d_tiles[1] = r->d_tiles[2] = nullptr;
+  r->d_small_idx = nullptr;
+  r->d_small_items = nullptr;
+  r->n_small_items = 0;
 }
+
+bool is_small(const RaggedState* r, int64_t s) { return r->sched.small >= 0 && s <= (int64_t(1) << r->sched.small); }
 
 // Image table, runs and tile lists for the current schedule; uploads them.
 int build_lists(RaggedState* r) {
@@ -103,8 +123,8 @@ int build_lists(RaggedState* r) {
   std::vector<std::pair<int64_t, int64_t>> spans;  // [first, last)
   int64_t first = 0, bytes = 0, off = 0, ws_off = 0;
   for (int64_t i = 0; i < n; ++i) {
-    const int64_t s = r->sizes[i], b = ws_elems_for(s) * 8;
-    if (r->sched.chunk > 0 && i > first && bytes + b > r->sched.chunk) {
+    const int64_t s = r->sizes[i], b = is_small(r, s) ? 0 : ws_elems_for(s) * 8;
+    if (r->sched.chunk > 0 && i > first && b > 0 && bytes + b > r->sched.chunk) {
       spans.push_back({first, i});
       first = i;
       bytes = 0;
@@ -131,6 +151,7 @@ int build_lists(RaggedState* r) {
       run.begin[p] = (int64_t)lists[p].size();
       for (int64_t i : idx) {
         const int64_t s = r->sizes[i];
+        if (is_small(r, s)) continue;
         // rows or columns per tile: one per transform, two per transform
         // in the first row pass of real input
         const int per = std::max(1, r->sched.block / threads_per_transform((int)s)) * (p == 0 && r->in_f32 ? 2 : 1);
@@ -140,6 +161,20 @@ int build_lists(RaggedState* r) {
       run.count[p] = (int64_t)lists[p].size() - run.begin[p];
     }
     r->runs.push_back(run);
+  }
+  // small images: largest side first, in items of at most ragged_small_ipw
+  // images of one side
+  std::vector<int> sidx;
+  std::vector<int2> items;
+  for (int64_t i = 0; i < n; ++i)
+    if (is_small(r, r->sizes[i])) sidx.push_back((int)i);
+  std::stable_sort(sidx.begin(), sidx.end(), [&](int a, int b) { return r->sizes[a] > r->sizes[b]; });
+  for (size_t a = 0; a < sidx.size();) {
+    const int lg = ilog2c((int)r->sizes[sidx[a]]), ipw = ragged_small_ipw(lg);
+    size_t b = a;
+    while (b < sidx.size() && b - a < (size_t)ipw && r->sizes[sidx[b]] == r->sizes[sidx[a]]) ++b;
+    items.push_back(make_int2((int)a, (int)(b - a)));
+    a = b;
   }
   if (n == 0) return FFT_OK;
   hipError_t e = hipMalloc(&r->d_imgs, n * sizeof(RaggedImage));
@@ -152,6 +187,17 @@ int build_lists(RaggedState* r) {
     e = hipMemcpy(r->d_tiles[p], lists[p].data(), lists[p].size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e);
   }
+  if (!items.empty()) {
+    e = hipMalloc(&r->d_small_idx, sidx.size() * sizeof(int));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_NOMEM : hip_fail(e);
+    e = hipMemcpy(r->d_small_idx, sidx.data(), sidx.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipMalloc(&r->d_small_items, items.size() * sizeof(int2));
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? FFT_ERR_NOMEM : hip_fail(e);
+    e = hipMemcpy(r->d_small_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e);
+    r->n_small_items = (int)items.size();
+  }
   return FFT_OK;
 }
 
@@ -161,6 +207,9 @@ hipError_t enqueue(const fftmi_plan* p, RaggedState* r, const void* in, void* ou
                    hipStream_t st, bool capturing = false) {
   const bool in_f32 = p->flags & FFT_IN_REAL_F32, out_f32 = p->flags & FFT_OUT_REAL_F32;
   const bool numpy = p->flags & FFT_NORM_NUMPY;
+  int small_grid = 0;
+  hipError_t se = ragged_small_grid(in_f32, out_f32, mk.kind, r->n_small_items, &small_grid);
+  if (se != hipSuccess) return se;
   std::vector<int> grids;
   for (const RaggedRun& run : r->runs)
     for (int pass = 0; pass < 3; ++pass) {
@@ -176,6 +225,21 @@ hipError_t enqueue(const fftmi_plan* p, RaggedState* r, const void* in, void* ou
   }
   size_t k = 0;
   hipError_t err = hipSuccess;
+  // small images: forked onto the side stream, so that in a captured graph
+  // they form a branch parallel to the passes of the larger images
+  const bool fork = r->n_small_items > 0 && capturing;
+  if (r->n_small_items > 0) {
+    hipStream_t ss = st;
+    if (fork) {
+      err = hipEventRecord(r->ev_fork, st);
+      if (err == hipSuccess) err = hipStreamWaitEvent(r->side_stream, r->ev_fork, 0);
+      ss = r->side_stream;
+    }
+    if (err == hipSuccess)
+      err = launch_ragged_small(in, in_f32, out, out_f32, r->d_imgs, r->d_small_idx, r->d_small_items,
+                                r->n_small_items, small_grid, mk, r->tw, numpy, ss);
+    if (fork && err == hipSuccess) err = hipEventRecord(r->ev_join, r->side_stream);
+  }
   for (const RaggedRun& run : r->runs) {
     for (int pass = 0; pass < 3 && err == hipSuccess; ++pass, ++k)
       err = launch_ragged_pass(pass, in, in_f32, static_cast<float2*>(ws), out, out_f32, r->d_imgs,
@@ -183,6 +247,7 @@ hipError_t enqueue(const fftmi_plan* p, RaggedState* r, const void* in, void* ou
                                mk, r->tw, numpy, st);
     if (err != hipSuccess) break;
   }
+  if (fork && err == hipSuccess) err = hipStreamWaitEvent(st, r->ev_join, 0);
   return err;
 }
 
@@ -211,7 +276,8 @@ std::string cache_key(const fftmi_plan* p, const RaggedState* r) {
 // schedule that would fail at every later exec.
 bool schedule_valid(const RaggedSchedule& s) {
   return (s.block == 128 || s.block == 256 || s.block == 512) && s.wg_cap >= 0 && s.wg_cap <= 64 &&
-         s.chunk >= 0 && s.chunk <= (int64_t(1) << 40) && (s.order == 0 || s.order == 1);
+         s.chunk >= 0 && s.chunk <= (int64_t(1) << 40) && (s.order == 0 || s.order == 1) && s.small >= -1 &&
+         s.small <= kRaggedSmallMaxLog2;
 }
 
 bool cache_lookup(const std::string& key, RaggedSchedule* s) {
@@ -226,7 +292,8 @@ bool cache_lookup(const std::string& key, RaggedSchedule* s) {
     std::string k;
     RaggedSchedule t;
     std::string rest;
-    if (ls >> k >> t.block >> t.wg_cap >> t.chunk >> t.order && k == key && !(ls >> rest) && schedule_valid(t)) {
+    if (ls >> k >> t.block >> t.wg_cap >> t.chunk >> t.order >> t.small && k == key && !(ls >> rest) &&
+        schedule_valid(t)) {
       *s = t;
       found = true;  // the last record of a key wins
     }
@@ -239,7 +306,7 @@ void cache_store(const std::string& key, const RaggedSchedule& s) {
   if (!path || !*path) return;
   std::lock_guard<std::mutex> lk(g_cache_mu);
   std::ofstream f(path, std::ios::app);
-  f << key << ' ' << s.block << ' ' << s.wg_cap << ' ' << s.chunk << ' ' << s.order << '\n';
+  f << key << ' ' << s.block << ' ' << s.wg_cap << ' ' << s.chunk << ' ' << s.order << ' ' << s.small << '\n';
 }
 
 bool valid_side(int64_t s) { return s >= 1 && s <= (int64_t(1) << kRaggedMaxLog2) && (s & (s - 1)) == 0; }
@@ -252,6 +319,9 @@ void destroy_ragged_state(fftmi_plan* p) {
   drop_graph(r);
   free_lists(r);
   if (r->cap_stream) (void)hipStreamDestroy(r->cap_stream);
+  if (r->side_stream) (void)hipStreamDestroy(r->side_stream);
+  if (r->ev_fork) (void)hipEventDestroy(r->ev_fork);
+  if (r->ev_join) (void)hipEventDestroy(r->ev_join);
   delete r;
   p->ragged = nullptr;
 }
@@ -264,16 +334,20 @@ int tune_ragged(fftmi_plan* p, const void* in, void* out, const fft_mask* mask, 
   int rc = mask_args(mask, p, &mk);
   if (rc != FFT_OK) return rc;
   std::vector<RaggedSchedule> cands;
-  for (int block : {256, 512})
-    for (int cap : {0, 2})
-      for (int64_t chunk : {int64_t(0), int64_t(128) << 20}) {
-        RaggedSchedule s;
-        s.block = block;
-        s.wg_cap = cap;
-        s.chunk = chunk;
-        s.order = 0;
-        cands.push_back(s);
-      }
+  // launch shape (threads per workgroup, workgroups per CU, runs) and
+  // transform shape: the largest side done in one pass from LDS
+  for (int small : {-1, 6, kRaggedSmallMaxLog2})
+    for (int block : {256, 512})
+      for (int cap : {0, 2})
+        for (int64_t chunk : {int64_t(0), int64_t(128) << 20}) {
+          RaggedSchedule s;
+          s.block = block;
+          s.wg_cap = cap;
+          s.chunk = chunk;
+          s.order = 0;
+          s.small = small;
+          cands.push_back(s);
+        }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
     if (e0) (void)hipEventDestroy(e0);
@@ -353,8 +427,23 @@ int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32
   e = hipStreamCreateWithFlags(&r->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e);
   p->ragged = r.get();
+  e = hipStreamCreateWithFlags(&r->side_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&r->ev_join, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    destroy_ragged_state(p.get());
+    r.release();
+    return hip_fail(e);
+  }
+
   RaggedSchedule cached;
   if (cache_lookup(cache_key(p.get(), r.get()), &cached)) r->sched = cached;
+  // FFTMI_RAGGED_SMALL (log2 of the largest single-pass side, -1 for none)
+  // overrides the single-pass limit, for tests and measurements
+  if (const char* sm = std::getenv("FFTMI_RAGGED_SMALL")) {
+    const int v = std::atoi(sm);
+    if (v >= -1 && v <= kRaggedSmallMaxLog2) r->sched.small = v;
+  }
   rc = build_lists(r.get());
   if (rc != FFT_OK) {
     destroy_ragged_state(p.get());
@@ -438,7 +527,7 @@ int fft_plan_tune(fft_plan_t p, const void* in, void* out, const fft_mask* mask,
   return FFT_OK;
 }
 
-int fft_plan_schedule(fft_plan_t p, int* block, int* wg_cap, int64_t* chunk_bytes, int* order) {
+int fft_plan_schedule(fft_plan_t p, int* block, int* wg_cap, int64_t* chunk_bytes, int* order, int* small_side) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 3 || !p->ragged) return FFT_ERR_UNSUPPORTED;
   const RaggedSchedule& s = p->ragged->sched;
@@ -446,6 +535,7 @@ int fft_plan_schedule(fft_plan_t p, int* block, int* wg_cap, int64_t* chunk_byte
   if (wg_cap) *wg_cap = s.wg_cap;
   if (chunk_bytes) *chunk_bytes = s.chunk;
   if (order) *order = s.order;
+  if (small_side) *small_side = s.small >= 0 ? 1 << s.small : 0;
   return FFT_OK;
 }
 

@@ -324,6 +324,143 @@ __global__ __launch_bounds__(kRaggedMaxBlock) __attribute__((amdgpu_waves_per_eu
   }
 }
 
+// ------------------------------------------------------------ small images
+// Images of side s <= 2^kRaggedSmallMaxLog2 in one pass from LDS: a
+// workgroup of kRaggedSmallBlock threads loads IPW(s) whole images of one
+// side into LDS (each row in a padded slot), transforms the rows (one
+// transform of 16 points per thread per row), writes the row spectra back
+// transposed, transforms the columns, applies the mask, transforms back,
+// transposes back, transforms the rows back and writes the images out:
+// 4 (or 8) bytes read and 8 (or 4) written per pixel instead of the three
+// HBM passes.  Each transform uses its own slot as exchange space, since its
+// data are in registers while it runs.  Work items are {first entry in the
+// index list, count} with the images of one item of one side.
+constexpr int small_ipw_c(int lg) {
+  return kRaggedSmallBlock / ((1 << lg) * threads_per_transform(1 << lg));
+}
+// bytes of one row slot: a transform's padded LDS region, spread over the
+// banks like the tiles that interleave as many transforms per wavefront
+constexpr int small_row_bytes(int lg) {
+  return lds_region_bytes(1 << lg, 64 / threads_per_transform(1 << lg) < 32 ? 64 / threads_per_transform(1 << lg) : 32);
+}
+constexpr int small_lds_c(int lg) { return small_ipw_c(lg) * (1 << lg) * small_row_bytes(lg); }
+constexpr int small_lds_max(int lg = 0) {
+  return lg > kRaggedSmallMaxLog2 ? 0
+                                   : (small_lds_c(lg) > small_lds_max(lg + 1) ? small_lds_c(lg) : small_lds_max(lg + 1));
+}
+constexpr int kSmallLds = kRgTwBytes + small_lds_max();
+static_assert(kSmallLds <= kLdsBytes, "small-image slots exceed LDS");
+
+template <int LG, int MK, bool IN_F32, bool OUT_F32>
+__device__ __forceinline__ void rg_small(const void* __restrict__ in, void* __restrict__ out,
+                                         const RaggedImage* __restrict__ imgs, const int* __restrict__ idx,
+                                         int2 item, const float2* __restrict__ tw, char* lds, const MaskArgs& mk0,
+                                         int numpy) {
+  constexpr int L = 1 << LG, E = elems_per_thread(L), TPT = L / E, PT = L * TPT;
+  constexpr int IPW = small_ipw_c(LG), RS = small_row_bytes(LG);
+  static_assert(IPW * PT == kRaggedSmallBlock, "every thread owns one row of one image slot");
+  // the thread's indices are laundered per item: otherwise the mask values and
+  // LDS addresses, which do not change from item to item, are hoisted out of
+  // the item loop and held (spilled) across the transforms
+  const int tid = (int)fresh(threadIdx.x), k = tid / PT, tl = tid - k * PT, rr = tl / TPT, j = tl - rr * TPT;
+  const bool live = k < item.y;
+  char* slot = lds + k * (L * RS);
+  char* row = slot + rr * RS;
+  auto at = [&](int r, int c) __attribute__((always_inline)) {
+    return reinterpret_cast<float2*>(slot + r * RS) + lds_pad(c);
+  };
+  int64_t off = 0;
+  if (live) off = imgs[idx[item.x + k]].off;
+  // load the image, coalesced (element e = i * PT + tl), into the row slots
+  lds_barrier();  // the previous item's readers of the slots are done
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = i * PT + tl;
+      float2 v;
+      if constexpr (IN_F32)
+        v = make_float2(__ldg(static_cast<const float*>(in) + off + e), 0.f);
+      else
+        v = __ldg(static_cast<const float2*>(in) + off + e);
+      *at(e / L, e % L) = v;
+    }
+  }
+  lds_barrier();
+  float2 a[E];
+  gather_natural<L, kBoth>(a, j, row);
+  float2 twr[reg_tw_count_mix<L>()];
+  load_twiddles_reg_mix<L>(twr, j, tw);
+  // rows forward, eq. 5's 1/s
+  fft_reg<L, false, kTwMix>(a, j, row, twr);
+  const float fs = rg_scale(LG, 1, numpy), is = rg_scale(LG, 0, numpy);
+  // transposed into the slots: slot row v holds column v of the spectrum
+  lds_barrier();
+#pragma unroll
+  for (int q = 0; q < E; ++q) *at(j + q * TPT, rr) = cscale(a[q], fs);
+  lds_barrier();
+  gather_natural<L, kBoth>(a, j, row);
+  // column rr: forward, mask, inverse
+  fft_reg<L, false, kTwMix>(a, j, row, twr);
+  MaskArgs mk = mk0;
+  mk.inv_n = mk.inv_m = 1.0f / (float)L;
+  const MaskEval<L, MK> me(mk, j, rr, L);
+  me.apply(a, j, mk);
+  fft_reg<L, true, kTwMix>(a, j, row, twr);
+  // transposed back to rows
+  lds_barrier();
+#pragma unroll
+  for (int q = 0; q < E; ++q) *at(j + q * TPT, rr) = a[q];
+  lds_barrier();
+  gather_natural<L, kBoth>(a, j, row);
+  // rows inverse, the 2D-IDFT's 1/s, out through the slots, coalesced
+  fft_reg<L, true, kTwMix>(a, j, row, twr);
+  lds_barrier();
+  scatter_natural<L, kBoth>(a, j, row);
+  lds_barrier();
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = i * PT + tl;
+      const float2 v = *at(e / L, e % L);
+      if constexpr (OUT_F32)
+        static_cast<float*>(out)[off + e] = v.x * is;
+      else
+        static_cast<float2*>(out)[off + e] = cscale(v, is);
+    }
+  }
+}
+
+#define FFTMI_RG_SMALL_CASES(X) X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7)
+
+template <int MK, bool IN_F32, bool OUT_F32>
+__global__ __launch_bounds__(kRaggedSmallBlock) void k_ragged_small(const void* __restrict__ in, void* __restrict__ out,
+                                                                     const RaggedImage* __restrict__ imgs,
+                                                                     const int* __restrict__ idx,
+                                                                     const int2* __restrict__ items, int nitems,
+                                                                     MaskArgs mk, TwTable tw, int numpy) {
+  char* lds = lds_base() + kRgTwBytes;
+  int cur_lg = -1;
+  for (int n = blockIdx.x; n < nitems; n += gridDim.x) {
+    const int2 it = items[n];
+    const int lg = imgs[idx[it.x]].lg;
+    switch (lg) {
+#define FFTMI_RG_SMALL(K)                                                                  \
+  case K:                                                                                  \
+    if (lg != cur_lg) {                                                                    \
+      lds_barrier();                                                                       \
+      rg_tw_lds<1 << K>(tw.p[K]);                                                          \
+      cur_lg = lg;                                                                         \
+    }                                                                                      \
+    rg_small<K, MK, IN_F32, OUT_F32>(in, out, imgs, idx, it, tw.p[K], lds, mk, numpy);     \
+    break;
+      FFTMI_RG_SMALL_CASES(FFTMI_RG_SMALL)
+#undef FFTMI_RG_SMALL
+      default:
+        break;
+    }
+  }
+}
+
 // Persistent grid: resident workgroups (occupancy, optionally capped per
 // CU), at most one per tile, a multiple of 8 where possible.
 std::mutex g_rg_mu;
@@ -399,6 +536,72 @@ hipError_t ragged_grid(int pass, bool in_f32, bool out_f32, int mask_kind, int b
   const void* fn = ragged_kernel(pass, in_f32, out_f32, mask_kind);
   if (!fn) return hipErrorInvalidValue;
   return rg_grid(fn, block, ragged_lds_bytes(block), wg_cap, ntiles, grid);
+}
+
+namespace {
+template <int MK>
+const void* small_kernel_for(bool in_f32, bool out_f32) {
+  if (in_f32)
+    return out_f32 ? reinterpret_cast<const void*>(k_ragged_small<MK, true, true>)
+                   : reinterpret_cast<const void*>(k_ragged_small<MK, true, false>);
+  return out_f32 ? reinterpret_cast<const void*>(k_ragged_small<MK, false, true>)
+                 : reinterpret_cast<const void*>(k_ragged_small<MK, false, false>);
+}
+const void* small_kernel(bool in_f32, bool out_f32, int mask_kind) {
+  switch (mask_kind) {
+    case FFT_MASK_GAUSSIAN:
+      return small_kernel_for<FFT_MASK_GAUSSIAN>(in_f32, out_f32);
+    case FFT_MASK_BUTTERWORTH:
+      return small_kernel_for<FFT_MASK_BUTTERWORTH>(in_f32, out_f32);
+    case FFT_MASK_NONE:
+      return small_kernel_for<FFT_MASK_NONE>(in_f32, out_f32);
+    default:
+      return nullptr;
+  }
+}
+template <int MK>
+void small_launch(bool in_f32, bool out_f32, int grid, hipStream_t st, const void* in, void* out,
+                  const RaggedImage* imgs, const int* idx, const int2* items, int nitems, const MaskArgs& mk,
+                  const TwTable& tw, int np) {
+  const dim3 g(grid), b(kRaggedSmallBlock);
+  if (in_f32 && out_f32)
+    hipLaunchKernelGGL((k_ragged_small<MK, true, true>), g, b, (size_t)kSmallLds, st, in, out, imgs, idx, items,
+                       nitems, mk, tw, np);
+  else if (in_f32)
+    hipLaunchKernelGGL((k_ragged_small<MK, true, false>), g, b, (size_t)kSmallLds, st, in, out, imgs, idx, items,
+                       nitems, mk, tw, np);
+  else if (out_f32)
+    hipLaunchKernelGGL((k_ragged_small<MK, false, true>), g, b, (size_t)kSmallLds, st, in, out, imgs, idx, items,
+                       nitems, mk, tw, np);
+  else
+    hipLaunchKernelGGL((k_ragged_small<MK, false, false>), g, b, (size_t)kSmallLds, st, in, out, imgs, idx, items,
+                       nitems, mk, tw, np);
+}
+}  // namespace
+
+int ragged_small_ipw(int lg) { return lg >= 0 && lg <= kRaggedSmallMaxLog2 ? small_ipw_c(lg) : 0; }
+
+hipError_t ragged_small_grid(bool in_f32, bool out_f32, int mask_kind, int nitems, int* grid) {
+  *grid = 0;
+  if (nitems <= 0) return hipSuccess;
+  const void* fn = small_kernel(in_f32, out_f32, mask_kind);
+  if (!fn) return hipErrorInvalidValue;
+  return rg_grid(fn, kRaggedSmallBlock, kSmallLds, 0, nitems, grid);
+}
+
+hipError_t launch_ragged_small(const void* in, bool in_f32, void* out, bool out_f32, const RaggedImage* imgs,
+                               const int* idx, const int2* items, int nitems, int grid, const MaskArgs& mk,
+                               const TwTable& tw, bool numpy, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (grid <= 0 || !small_kernel(in_f32, out_f32, mk.kind)) return hipErrorInvalidValue;
+  const int np = numpy ? 1 : 0;
+  if (mk.kind == FFT_MASK_GAUSSIAN)
+    small_launch<FFT_MASK_GAUSSIAN>(in_f32, out_f32, grid, st, in, out, imgs, idx, items, nitems, mk, tw, np);
+  else if (mk.kind == FFT_MASK_BUTTERWORTH)
+    small_launch<FFT_MASK_BUTTERWORTH>(in_f32, out_f32, grid, st, in, out, imgs, idx, items, nitems, mk, tw, np);
+  else
+    small_launch<FFT_MASK_NONE>(in_f32, out_f32, grid, st, in, out, imgs, idx, items, nitems, mk, tw, np);
+  return hipGetLastError();
 }
 
 hipError_t launch_ragged_pass(int pass, const void* in, bool in_f32, float2* ws, void* out, bool out_f32,

@@ -14,11 +14,11 @@
 
 namespace fftmi {
 
-int widest_cols_tile(int log2L, int cols, int wmax) {
+int widest_cols_tile(int log2L, int cols, int wmax, int max_threads) {
   const int tpt = threads_per_transform(1 << log2L);
+  const int cap = max_threads > 0 ? max_threads : max_block_threads(log2L);
   int w = 1;
-  while (w * 2 <= wmax && w * 2 <= cols && (w * 2) * tpt <= max_block_threads(log2L) &&
-         lds_bytes_cols(log2L, w * 2) <= kLdsBytes)
+  while (w * 2 <= wmax && w * 2 <= cols && (w * 2) * tpt <= cap && lds_bytes_cols(log2L, w * 2) <= kLdsBytes)
     w *= 2;
   return w;
 }

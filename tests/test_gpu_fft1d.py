@@ -95,7 +95,7 @@ def test_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
-_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W")
+_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2")
 
 
 def _fft_with(env, x, direction):
@@ -134,18 +134,40 @@ def test_fourstep_layout_knobs(lg):
     x = synth.uniform_complex((batch, n), 40 + lg)
     xd = to_dev(x)
     ref = oracle.fft(x, threads=8)
-    first = None
-    for pad in (0, 32, 96):
-        for w in (16, 4, 1):
-            env = dict(FFTMI_FS_PAD=pad, FFTMI_FS_W=w)
-            announce("fft1d four-step n=2^%d %s" % (lg, env))
-            got, plan = _fft_with(env, xd, B.FFT_FORWARD)
-            assert plan.workspace_bytes >= batch * n2 * (n1 + pad) * 8, env
-            assert rel_l2(got, ref, 1) < TOL, env
-            if first is None:
-                first = got
-            else:
-                assert np.array_equal(got, first), env
+    # bit-identical among the settings of one kernel build (threads per tile);
+    # the 1024-thread build is another compilation of the transform, whose
+    # floating-point contractions may differ in the last bit
+    first = {}
+    for pad, w, thr in [(p_, w_, 512) for p_ in (0, 32, 96) for w_ in (16, 4, 1)] + [(0, 16, 1024), (32, 16, 1024)]:
+        env = dict(FFTMI_FS_PAD=pad, FFTMI_FS_W=w, FFTMI_FS_THREADS1=thr, FFTMI_FS_THREADS2=thr)
+        announce("fft1d four-step n=2^%d %s" % (lg, env))
+        got, plan = _fft_with(env, xd, B.FFT_FORWARD)
+        assert plan.workspace_bytes >= batch * n2 * (n1 + pad) * 8, env
+        assert rel_l2(got, ref, 1) < TOL, env
+        if thr not in first:
+            first[thr] = got
+        else:
+            assert np.array_equal(got, first[thr]), env
+    if len(first) == 2:
+        assert rel_l2(first[1024], first[512], 1) < 1e-6
+
+
+@pytest.mark.parametrize("lg", [19, 20, 22])
+def test_fourstep_wide_tiles(lg):
+    """1024-thread four-step tiles (twice the columns per tile) against the
+    oracle in both directions, and against the 512-thread tiles."""
+    from paper_cs_0103001_amd import _binding as B
+    x = synth.uniform_complex((2, 1 << lg), (14, lg))
+    xd = to_dev(x)
+    for direction, ref in ((B.FFT_FORWARD, oracle.fft(x, threads=8)), (B.FFT_INVERSE, oracle.ifft(x, threads=8))):
+        outs = []
+        for t1, t2 in ((512, 512), (512, 1024), (1024, 512), (1024, 1024)):
+            announce("fft1d four-step n=2^%d dir %d threads %d/%d" % (lg, direction, t1, t2))
+            got, plan = _fft_with(dict(FFTMI_FS_THREADS1=t1, FFTMI_FS_THREADS2=t2), xd, direction)
+            assert rel_l2(got, ref, 1) < TOL
+            outs.append(got)
+        for o in outs[1:]:
+            assert rel_l2(o, outs[0], 1) < 1e-6
 
 
 @pytest.mark.parametrize("lg", [23, 24])

@@ -214,19 +214,56 @@ def test_tune_cache_records_are_validated(tmp_path, monkeypatch):
     announce("tune cache validation")
     api.tune_ragged(x, sizes, mask)
     key = cache.read_text().split()[0]
-    default = {"block": 256, "wg_cap": 0, "chunk_bytes": 0, "order": 0}
-    for bad in ("7 0 0 0", "256 -1 0 0", "256 0 -5 0", "256 0 0 9", "512 0 0 0 extra", "256 0"):
+    default = {"block": 256, "wg_cap": 0, "chunk_bytes": 0, "order": 0, "small_side": 128}
+    for bad in ("7 0 0 0 7", "256 -1 0 0 7", "256 0 -5 0 7", "256 0 0 9 7", "512 0 0 0 7 extra", "256 0",
+                "256 0 0 0 8", "256 0 0 0 -2", "512 2 0 1"):
         cache.write_text("%s %s\n" % (key, bad))
         h = B.fft_plan_ragged(sizes, B.FFT_IN_REAL_F32)
         try:
             assert B.fft_plan_schedule(h) == default, bad
         finally:
             B.fft_plan_destroy(h)
-    cache.write_text("%s 512 2 0 1\n" % key)
+    cache.write_text("%s 512 2 0 1 6\n" % key)
     h = B.fft_plan_ragged(sizes, B.FFT_IN_REAL_F32)
     try:
-        assert B.fft_plan_schedule(h) == {"block": 512, "wg_cap": 2, "chunk_bytes": 0, "order": 1}
+        assert B.fft_plan_schedule(h) == {"block": 512, "wg_cap": 2, "chunk_bytes": 0, "order": 1, "small_side": 64}
     finally:
         B.fft_plan_destroy(h)
     monkeypatch.delenv("FFTMI_TUNE_CACHE")
     _check(to_host(api.filter_ragged(x, sizes, mask)), imgs, sizes)
+
+
+@pytest.mark.parametrize("small", [-1, 5, 7])
+def test_ragged_single_pass_limit(small, monkeypatch):
+    """Every side with the single-pass LDS path off, up to 32 and up to 128
+    (FFTMI_RAGGED_SMALL, log2 of the largest such side): each image against
+    the oracle, with real and complex input, c64 and f32 output, and a batch
+    with more images of one side than a work item holds (64^2: 4 per item,
+    32^2: 16), graph replays and eager launches alike."""
+    from paper_cs_0103001_amd import _binding as B
+    from paper_cs_0103001_amd import api
+    import torch
+    monkeypatch.setenv("FFTMI_RAGGED_SMALL", str(small))
+    sizes = [128, 64, 64, 64, 64, 64, 32] * 3 + [32] * 14 + [16, 8, 4, 2, 1, 256, 512, 128, 1]
+    for cplx, real_out in ((False, False), (True, True)):
+        imgs, flat = _images(sizes, seed0=900 + small, complex_input=cplx)
+        x = to_dev(flat)
+        flags = (0 if cplx else B.FFT_IN_REAL_F32) | (B.FFT_OUT_REAL_F32 if real_out else 0)
+        for graph in ("1", "0"):
+            monkeypatch.setenv("FFTMI_RAGGED_GRAPH", graph)
+            h = B.fft_plan_ragged(sizes, flags)
+            try:
+                sched = B.fft_plan_schedule(h)
+                assert sched["small_side"] == (0 if small < 0 else 1 << small)
+                out = torch.empty(x.numel(), dtype=torch.float32 if real_out else torch.complex64, device="cuda")
+                ws = torch.empty(max(B.fft_workspace_size(h), 16), dtype=torch.uint8, device="cuda")
+                mk = B.make_mask("butterworth", cutoff=0.15, order=4)
+                announce("ragged single-pass limit %d complex %s graph %s" % (small, cplx, graph))
+                for _ in range(2):
+                    B.fft2d_filter_ragged(h, api._ptr(x), api._ptr(out), mk, api._ptr(ws), api._stream(x.device))
+                got = to_host(out)
+                for g, im, s in zip(_split(got, sizes), imgs, sizes):
+                    ref = oracle.filter2(im, oracle.mask_butterworth(s, s, 0.15, 4), threads=4)
+                    assert rel_l2(g, ref.real if real_out else ref, 2) < TOL, (s, small)
+            finally:
+                B.fft_plan_destroy(h)
