@@ -374,8 +374,39 @@ def main():
                             "Mpx": round(pxr / 1e6, 2), "ms_per_step": round(ms_r, 4), "GB/s": round(gbs_r, 1),
                             "hbm_frac": round(gbs_r / HBM_PEAK_GBS, 4), "images_per_s": round(512 / (ms_r * 1e-3), 1),
                             "ns_per_px": round(ms_r * 1e6 / pxr, 4), "ns_per_px_plain_4096": round(ms * 1e6 / px, 4),
-                            "schedule": sched, "launch": "hipGraph replay (3 persistent launches per run)"}
+                            "schedule": sched,
+                            "launch": "hipGraph replay (3 persistent launches per run%s)" % (
+                                ", plus a parallel single-pass launch for sides <= %d" % sched["small_side"]
+                                if sched.get("small_side") else "")}
         del xr, outr, wsr
+
+        # small images: the single-pass LDS path against the three passes on
+        # a batch of sides 32..128 (the single-pass limit set per plan)
+        rng = np.random.default_rng(33)
+        ssizes = [int(v) for v in rng.choice([32, 64, 128], size=2048)]
+        sflat = np.concatenate([synth.ragged_image(5000 + i, sz).reshape(-1) for i, sz in enumerate(ssizes)])
+        xs_ = torch.from_numpy(sflat).to(dev)
+        outs_ = torch.empty(xs_.numel(), dtype=torch.complex64, device=dev)
+        spx = sum(v * v for v in ssizes)
+        small = {}
+        for label, lim in (("three_pass", "-1"), ("single_pass", "7")):
+            os.environ["FFTMI_RAGGED_SMALL"] = lim
+            try:
+                hs = B.fft_plan_ragged(ssizes, B.FFT_IN_REAL_F32)
+            finally:
+                os.environ.pop("FFTMI_RAGGED_SMALL", None)
+            wss = torch.empty(max(B.fft_workspace_size(hs), 16), dtype=torch.uint8, device=dev)
+            sp = [ctypes.c_void_p(t.data_ptr()) for t in (xs_, outs_, wss)]
+            ms_s = timed(torch, lambda: B.fft2d_filter_ragged(hs, sp[0], sp[1], rmk, sp[2], st), Kr, 2, WARM_MS / 2)
+            small[label] = {"ms_per_step": round(ms_s, 4), "images_per_s": round(len(ssizes) / (ms_s * 1e-3), 1),
+                            "ns_per_px": round(ms_s * 1e6 / spx, 4)}
+            B.fft_plan_destroy(hs)
+            del wss
+        result["ragged"]["small_images"] = dict(
+            small, workload="2048 star fields, sides uniform from {32, 64, 128} (seed 33), Gaussian sigma_f 0.1",
+            Mpx=round(spx / 1e6, 2),
+            speedup_single_pass=round(small["three_pass"]["ms_per_step"] / small["single_pass"]["ms_per_step"], 3))
+        del xs_, outs_
 
     # ---------------------------------------------------------- CPU oracle
     if not args.no_cpu:

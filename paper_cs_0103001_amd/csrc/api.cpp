@@ -323,8 +323,8 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
         }
         return dflt;
       };
-      p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, wmax, fs_threads("FFTMI_FS_THREADS1", 512));
-      p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, wmax, fs_threads("FFTMI_FS_THREADS2", 512));
+      p->w1 = widest_cols_tile(p->log_n1, 1 << p->log_n2, wmax, fs_threads("FFTMI_FS_THREADS1", 1024));
+      p->w2 = widest_cols_tile(p->log_n2, 1 << p->log_n1, wmax, fs_threads("FFTMI_FS_THREADS2", 1024));
       rc = fourstep_tables(t, p->log_n, p->log_n1, &p->tw_fs);
       if (rc != FFT_OK) return rc;
       // the intermediate [N2][N1] rows get a padded stride, so that the

@@ -863,8 +863,15 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
   const int tmask = (1 << ltiles) - 1;
   constexpr bool PF = TPT <= 512 && !WIDE;  // 1024-thread workgroups have no room for a second tile
   float2 a[E], nx[PF ? E : 1];
+  // tile t -> (batch entry, column tile).  Pass one takes the batch entries
+  // of one column tile in a row (t = column tile * entries + entry), so that
+  // the workgroups on one XCD read the tile's factors W_N^{k1 n2} from its L2
+  // after the first entry, instead of once per entry from memory.
+  const int nent = ntiles >> ltiles;
+  auto entry_of = [&](int t) __attribute__((always_inline)) { return TT ? t % nent : t >> ltiles; };
+  auto ctile_of = [&](int t) __attribute__((always_inline)) { return TT ? t / nent : t & tmask; };
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
-    const float2* b = in + (int64_t)(t >> ltiles) * ib + (t & tmask) * w;
+    const float2* b = in + (int64_t)entry_of(t) * ib + ctile_of(t) * w;
     {
       const unsigned f_lane = fresh(lane);
 #pragma unroll
@@ -883,8 +890,8 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
     } else {
       load(a, t);
     }
-    const int64_t bo = (int64_t)(t >> ltiles) * ob;
-    const int c0 = (t & tmask) * w;
+    const int64_t bo = (int64_t)entry_of(t) * ob;
+    const int c0 = ctile_of(t) * w;
     fft_reg<L, INV, S::TWM>(a, j, x, tw);
     if constexpr (TT) {
       // transposed store through LDS: out[n2][k1], contiguous along k1
@@ -920,9 +927,14 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
       }
       float2* b = out + bo + (int64_t)c0 * ors;
       const float2* tf = tfs + (int64_t)c0 * L;  // rows n2 = c0 .. c0 + w - 1
+      // the store indices come from an opaque thread index: otherwise their
+      // addresses are computed once, before the tile loop, and held in
+      // registers across the transform (pass one then needs 150-240 VGPRs
+      // instead of 100-150)
+      const int t0 = (int)fresh((unsigned)tid);
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int idx = tid + e * nthr;
+        const int idx = t0 + e * nthr;
         const float2 wv = tf[(unsigned)idx];  // W_N^{k1 n2}, k1 = idx % L, n2 = c0 + idx / L
         b[(unsigned)((idx >> lL) * ors + (idx & (L - 1)))] = cscale(cmul_tw<INV>(o[e], wv), scale);
       }

@@ -225,9 +225,9 @@ hipError_t enqueue(const fftmi_plan* p, RaggedState* r, const void* in, void* ou
   }
   size_t k = 0;
   hipError_t err = hipSuccess;
-  // small images: forked onto the side stream, so that in a captured graph
-  // they form a branch parallel to the passes of the larger images
-  const bool fork = r->n_small_items > 0 && capturing;
+  // small images: forked onto the side stream, so that they run beside the
+  // passes of the larger images (in a captured graph: a parallel branch)
+  const bool fork = r->n_small_items > 0;
   if (r->n_small_items > 0) {
     hipStream_t ss = st;
     if (fork) {
@@ -249,6 +249,31 @@ hipError_t enqueue(const fftmi_plan* p, RaggedState* r, const void* in, void* ou
   }
   if (fork && err == hipSuccess) err = hipStreamWaitEvent(st, r->ev_join, 0);
   return err;
+}
+
+// Capture one call's launches (on the plan's capture stream) into an
+// instantiated graph.
+hipError_t capture(const fftmi_plan* p, RaggedState* r, const void* in, void* out, void* ws, const MaskArgs& mk,
+                   hipGraph_t* graph, hipGraphExec_t* exec) {
+  *graph = nullptr;
+  *exec = nullptr;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t le = enqueue(p, r, in, out, ws, mk, r->cap_stream, true);
+  hipError_t e = hipSuccess;
+  if (hipStreamIsCapturing(r->cap_stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
+    e = hipStreamEndCapture(r->cap_stream, graph);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (*graph) (void)hipGraphDestroy(*graph);
+    *graph = nullptr;
+    return le != hipSuccess ? le : e;
+  }
+  e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(*graph);
+    *graph = nullptr;
+    *exec = nullptr;
+  }
+  return e;
 }
 
 // ----------------------------------------------------------- tuning cache
@@ -363,13 +388,21 @@ int tune_ragged(fftmi_plan* p, const void* in, void* out, const fft_mask* mask, 
       status = rc;
       break;
     }
-    hipError_t e = enqueue(p, r, in, out, ws, mk, st);  // warm-up
+    // each candidate runs the way calls will run it: as a graph replay
+    // (or eagerly when graphs are off), once to warm up, then three timed
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    hipError_t e = r->use_graph ? capture(p, r, in, out, ws, mk, &g, &x) : hipSuccess;
+    auto run = [&]() { return x ? hipGraphLaunch(x, st) : enqueue(p, r, in, out, ws, mk, st); };
+    if (e == hipSuccess) e = run();
     if (e == hipSuccess) e = hipEventRecord(e0, st);
-    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = enqueue(p, r, in, out, ws, mk, st);
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = run();
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     float ms = 0.f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       status = hip_fail(e);
       break;
@@ -481,22 +514,8 @@ int fft2d_filter_ragged(fft_plan_t p, const void* in, void* out, const fft_mask*
                     std::memcmp(&r->g_mask, &mk, sizeof(MaskArgs)) == 0;
   if (!same) {
     drop_graph(r);
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t le = enqueue(p, r, in, out, workspace, mk, r->cap_stream, true);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipSuccess;
-    if (hipStreamIsCapturing(r->cap_stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive)
-      e = hipStreamEndCapture(r->cap_stream, &g);
-    if (le != hipSuccess || e != hipSuccess) {
-      if (g) (void)hipGraphDestroy(g);
-      return hip_fail(le != hipSuccess ? le : e);
-    }
-    r->graph = g;
-    e = hipGraphInstantiate(&r->exec, r->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      drop_graph(r);
-      return hip_fail(e);
-    }
+    hipError_t e = capture(p, r, in, out, workspace, mk, &r->graph, &r->exec);
+    if (e != hipSuccess) return hip_fail(e);
     r->g_in = in;
     r->g_out = out;
     r->g_ws = workspace;
