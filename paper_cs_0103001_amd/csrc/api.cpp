@@ -43,7 +43,7 @@ struct DevTables {
   float2* blob = nullptr;
   int64_t off[kMaxLog2Row + 1] = {};
   int64_t off_lds[kMaxLog2Row + 1] = {};  // LDS-layout copies, after the global-layout tables
-  std::map<int, float2*> fourstep;  // log2 N -> [N2][N1] factors of the four-step split
+  std::map<int, float2*> fourstep;  // 32 log2 N + log2 N1 -> [N2][N1] factors of that four-step split
 };
 
 namespace {
@@ -135,7 +135,8 @@ void plan_unregister(fftmi_plan* p) {
 // exact integer k1 n2 mod N in FP64, rounded once.
 int fourstep_tables(DevTables* t, int log2N, int log2N1, const float2** tab) {
   std::lock_guard<std::mutex> lk(g_mu);
-  auto it = t->fourstep.find(log2N);
+  const int key = 32 * log2N + log2N1;
+  auto it = t->fourstep.find(key);
   if (it == t->fourstep.end()) {
     const int64_t N = int64_t(1) << log2N, n1 = int64_t(1) << log2N1, n2 = N / n1;
     std::vector<float2> z((size_t)N), host((size_t)N);
@@ -150,7 +151,7 @@ int fourstep_tables(DevTables* t, int log2N, int log2N1, const float2** tab) {
       (void)hipFree(d);
       return hip_fail(e);
     }
-    it = t->fourstep.emplace(log2N, static_cast<float2*>(d)).first;
+    it = t->fourstep.emplace(key, static_cast<float2*>(d)).first;
   }
   *tab = it->second;
   return FFT_OK;
@@ -308,6 +309,12 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
     if (p->log_n > kMaxLog2Row) {
       p->fourstep = true;
       p->log_n1 = p->log_n / 2;
+      // FFTMI_FS_LOG_N1 moves the split N = N1 N2 (both lengths within the
+      // four-step kernels' 2^7 .. 2^12), for measurements
+      if (const char* e = std::getenv("FFTMI_FS_LOG_N1")) {
+        const int v = std::atoi(e);
+        if (v >= 7 && v <= 12 && p->log_n - v >= 7 && p->log_n - v <= 12) p->log_n1 = v;
+      }
       p->log_n2 = p->log_n - p->log_n1;
       int wmax = 16;
       if (const char* e = std::getenv("FFTMI_FS_W")) {

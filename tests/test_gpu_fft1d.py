@@ -95,7 +95,7 @@ def test_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
-_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2")
+_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2", "FFTMI_FS_LOG_N1")
 
 
 def _fft_with(env, x, direction):
@@ -168,6 +168,23 @@ def test_fourstep_wide_tiles(lg):
             outs.append(got)
         for o in outs[1:]:
             assert rel_l2(o, outs[0], 1) < 1e-6
+
+
+@pytest.mark.parametrize("lg", [15, 20, 22])
+def test_fourstep_uneven_splits(lg):
+    """Every split N = N1 N2 with both lengths in 2^7 .. 2^12, one plan after
+    another in one process (each split has its own table of W_N^{k1 n2}),
+    forward and inverse against the oracle."""
+    from paper_cs_0103001_amd import _binding as B
+    x = synth.uniform_complex((2, 1 << lg), (15, lg))
+    xd = to_dev(x)
+    refs = {B.FFT_FORWARD: oracle.fft(x, threads=8), B.FFT_INVERSE: oracle.ifft(x, threads=8)}
+    for n1 in range(max(7, lg - 12), min(12, lg - 7) + 1):
+        for direction, ref in refs.items():
+            announce("fft1d four-step n=2^%d split 2^%d x 2^%d dir %d" % (lg, n1, lg - n1, direction))
+            got, plan = _fft_with(dict(FFTMI_FS_LOG_N1=n1), xd, direction)
+            assert plan.workspace_bytes >= 2 * (1 << lg) * 8
+            assert rel_l2(got, ref, 1) < TOL, (n1, direction)
 
 
 @pytest.mark.parametrize("lg", [23, 24])
