@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "4096^2 FFT-filter-IFFT GB/s (% HBM peak); batched, fwd+bwd vs plain"
 HBM_PEAK_GBS = 8000.0
 # the sections after the headline, in the order they run
-SECTIONS = ("copy", "half_spectrum", "cold", "batched", "fwd_bwd", "sweep_1d", "ragged")
+SECTIONS = ("copy", "half_spectrum", "tensor_mask", "cold", "batched", "fwd_bwd", "sweep_1d", "ragged")
 # untimed wall time each section after the headline runs before timing
 WARM_MS = 60.0
 N = M = 4096
@@ -243,6 +243,25 @@ def main():
                                                  "the bytes this path moves; the 44 B/px equivalent is for comparison "
                                                  "with the headline only")
         del x
+
+    if want("tensor_mask"):
+        # ------------------------------------------- the mask as a tensor
+        # the same 4096^2 filter with the Butterworth values given as a
+        # float32 [N][M] tensor (the learnable-mask path): 48 B/px (+4 for
+        # the mask) plus the per-call transposed copy of the mask (8 B/px)
+        import oracle
+        mt_t = torch.from_numpy(oracle.mask_butterworth(N, M, 0.15, 4).astype(np.float32)).to(dev)
+        mkt = B.make_mask("tensor", data_ptr=mt_t.data_ptr())
+        x = torch.from_numpy(img).to(dev)
+        out = torch.empty((N, M), dtype=torch.complex64, device=dev)
+        ws = plan.workspace()
+        tp = [ctypes.c_void_p(t.data_ptr()) for t in (x, out, ws)]
+        ms_t = timed(torch, lambda: B.fft2d_filter(plan.h, tp[0], tp[1], mkt, tp[2], st), K, 10, WARM_MS)
+        result["tensor_mask"] = {"ms_per_step": round(ms_t, 5), "GB/s_44B_model": round(bytes_step / (ms_t * 1e-3) / 1e9, 1),
+                                 "time_vs_analytic": round(ms_t / ms, 3),
+                                 "note": "Butterworth values as a float32 tensor mask (transposed per call for "
+                                         "4096-point columns)"}
+        del mt_t, x, out, ws
 
     if want("cold"):
         # --------------------------------------------------------- cold cache

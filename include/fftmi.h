@@ -283,8 +283,9 @@ int fft_plan_layout(fft_plan_t plan, int* rows_per_block, int* cols_per_tile, in
  * later calls allocate nothing at all.  The caller still passes in and out
  * (as fft2d_filter, in may equal out).  A plan whose filter needs more than
  * the array (one chunk's blocked intermediate: up to a 4096 x 4096 image, or
- * a batch chunk of 128 MiB; a padded plan's whole workspace) returns
- * FFT_ERR_SCRATCH before any device work.  Every call on one device shares
+ * a batch chunk of 128 MiB; with a tensor mask and N >= 2048, N * M * 4 bytes
+ * more for the mask's transposed copy; a padded plan's whole workspace)
+ * returns FFT_ERR_SCRATCH before any device work.  Every call on one device shares
  * that device's array and leaves the last call's contents in it: calls that
  * overlap on one device (other streams, other threads) race and must be
  * serialised by the caller.  Nothing in the array needs to start at zero.

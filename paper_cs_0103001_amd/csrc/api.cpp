@@ -231,6 +231,10 @@ int mask_args(const fft_mask* mk, const fftmi_plan* p, MaskArgs* out) { return f
 // multiple of 4 KiB puts the row blocks a column tile reads on the same
 // memory channels; 32 extra elements (256 bytes) spread them.  FFTMI_BLOCK_PAD
 // (a multiple of 32, up to 4096) overrides the pad for tuning.
+size_t fftmi::maskt_bytes(const fftmi_plan* p) {
+  return p->kind == 2 && !p->half && p->n >= 2048 ? (size_t)p->n * (size_t)p->m * sizeof(float) : 0;
+}
+
 int64_t fftmi::block_pad(int64_t stride) {
   if (const char* e = std::getenv("FFTMI_BLOCK_PAD")) {
     const long v = std::atol(e);
@@ -372,6 +376,13 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       const int64_t nparts = std::max<int64_t>(batch * N, 1);
       p->loss_mid_off = (p->loss_off + (size_t)nparts * sizeof(float) + 255) & ~(size_t)255;
       p->ws_bytes = p->loss_mid_off + (size_t)sum_partials_scratch(nparts) * sizeof(double);
+      // columns of 2048 points or more go in tiles of one or two columns, so
+      // a row-major tensor mask would be read one float per row; such plans
+      // keep room for a transposed copy, made per call
+      if (N >= 2048) {
+        p->maskt_off = (p->ws_bytes + 255) & ~(size_t)255;
+        p->ws_bytes = p->maskt_off + maskt_bytes(p.get());
+      }
     }
   }
   plan_register(p.get());
@@ -529,7 +540,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
 
 // stages: bit 0 = row pass, bit 1 = column pass, bit 2 = inverse row pass
 int fftmi::filter_run(fftmi_plan* p, const void* in, void* out, const fft_mask* mask, void* spectrum,
-                      void* workspace, void* stream, int stages, int64_t chunk_images) {
+                      void* workspace, void* stream, int stages, int64_t chunk_images, float* maskt) {
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
   MaskArgs mk;
@@ -557,6 +568,13 @@ int fftmi::filter_run(fftmi_plan* p, const void* in, void* out, const fft_mask* 
   const bool pair = in_f32 && p->rb >= 2;
   Launch lr = launch_for(st, p->tables, p->log_m);
   Launch lcn = launch_for(st, p->tables, p->log_n);
+  if (mk.kind == FFT_MASK_TENSOR_F32 && p->maskt_off && (stages & 2)) {
+    float* mt = maskt ? maskt : reinterpret_cast<float*>(static_cast<char*>(workspace) + p->maskt_off);
+    hipError_t e = launch_transpose_f32(mk.data, mt, p->n, p->m, st);
+    if (e != hipSuccess) return hip_fail(e);
+    mk.data = mt;
+    mk.tensor_cm = 1;
+  }
   // Section 6's padding: the caller's n0 x m0 images are zero-padded into
   // the workspace, filtered there, and the result cropped back into `out`.
   void* final_out = out;
@@ -709,6 +727,13 @@ int fft2d_filter_mse(fft_plan_t p, const float* x, const float* c, const float* 
   mk.inv_m = 1.0f / (float)p->m;
   Launch lr = launch_for(st, p->tables, p->log_m);
   Launch lcn = launch_for(st, p->tables, p->log_n);
+  if (p->maskt_off && p->batch > 0) {
+    float* mt = reinterpret_cast<float*>(static_cast<char*>(workspace) + p->maskt_off);
+    hipError_t e = launch_transpose_f32(mask, mt, p->n, p->m, st);
+    if (e != hipSuccess) return hip_fail(e);
+    mk.data = mt;
+    mk.tensor_cm = 1;
+  }
   const int64_t plane = p->n * p->m;
   int64_t nparts = 0;
   for (int64_t b0 = 0; b0 < p->batch; b0 += p->chunk) {

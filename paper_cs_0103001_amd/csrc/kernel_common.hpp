@@ -373,13 +373,18 @@ struct MaskEval<L, FFT_MASK_DISC> {
 };
 
 // Tensor masks: H[u][v] = data[u*M + v], read for the thread's column after
-// the forward transform (base: column v of the tile, stride M per row).
+// the forward transform (base: column v of the tile, stride M per row); or,
+// with tensor_cm, from the transposed copy data[v*L + u], whose column is
+// contiguous (a wavefront's reads of one element index cover consecutive
+// rows of one column instead of one float per row).
 template <int L>
 struct MaskEval<L, FFT_MASK_TENSOR_F32> {
   const float* col;
   unsigned lane, qs;
   __device__ __forceinline__ MaskEval(const MaskArgs& mk, int j, int v, int M)
-      : col(mk.data + v), lane((unsigned)(j * M)), qs((unsigned)((L / elems_per_thread(L)) * M)) {}
+      : col(mk.tensor_cm ? mk.data + (int64_t)v * L : mk.data + v),
+        lane(mk.tensor_cm ? (unsigned)j : (unsigned)(j * M)),
+        qs(mk.tensor_cm ? (unsigned)(L / elems_per_thread(L)) : (unsigned)((L / elems_per_thread(L)) * M)) {}
   __device__ __forceinline__ void apply(float2 (&a)[elems_per_thread(L)], int, const MaskArgs& mk) const {
     const unsigned l = fresh(lane);
 #pragma unroll

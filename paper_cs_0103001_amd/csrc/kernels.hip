@@ -702,6 +702,20 @@ __global__ __launch_bounds__(256) void k_unblock(const float2* __restrict__ ws, 
   }
 }
 
+// out[v][u] = in[u][v] for a float32 [N][M] array: 64 x 64 tiles through
+// LDS (padded rows), each read and written along contiguous 256-byte rows.
+__global__ __launch_bounds__(256) void k_transpose_f32(const float* __restrict__ in, float* __restrict__ out,
+                                                        int64_t N, int64_t M) {
+  __shared__ float t[64][65];
+  const int64_t u0 = (int64_t)blockIdx.y * 64, v0 = (int64_t)blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4)
+    if (u0 + r < N && v0 + tx < M) t[r][tx] = __ldg(in + (u0 + r) * M + v0 + tx);
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4)
+    if (v0 + r < M && u0 + tx < N) out[(v0 + r) * N + u0 + tx] = t[tx][r];
+}
+
 // Section 6 front end: zero padding of [B][n0][m0] images to [B][N][M]
 // (appended rows and columns), and cropping back.  Element-wise, coalesced.
 template <typename T>
@@ -1413,6 +1427,13 @@ hipError_t launch_crop(const void* in, void* out, bool f32, int64_t nimg, int n0
   else
     hipLaunchKernelGGL(k_crop<float2>, elementwise_grid(total), dim3(256), 0, st, static_cast<const float2*>(in),
                        static_cast<float2*>(out), total, n0, m0, log2N, log2M);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose_f32(const float* in, float* out, int64_t N, int64_t M, hipStream_t st) {
+  if (N <= 0 || M <= 0) return hipSuccess;
+  const dim3 g((unsigned)((M + 63) / 64), (unsigned)((N + 63) / 64));
+  hipLaunchKernelGGL(k_transpose_f32, g, dim3(256), 0, st, in, out, N, M);
   return hipGetLastError();
 }
 

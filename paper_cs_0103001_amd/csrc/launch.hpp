@@ -25,6 +25,7 @@ struct MaskArgs {
   double c1, c2;        // disc centre (bin units)
   float inv_n, inv_m;   // 1/N and 1/M (exact powers of two) for the frequency grid
   float tensor_bias;    // added to every tensor-mask value (-1: the fused MSE form's m - 1)
+  int tensor_cm;        // the tensor mask is stored transposed, [M][N] (column v contiguous)
 };
 
 struct Launch {
@@ -85,6 +86,9 @@ hipError_t launch_cols_filter(int log2L, float2* ws, float2* save, int64_t nimg,
 // Column pass on the blocked layout: one unscaled transform, in place.
 hipError_t launch_cols_fft(int log2L, bool inv, float2* ws, int64_t nimg, int M, int rb, unsigned bs, int w,
                            const Launch& lc);
+
+// out[v][u] = in[u][v] for a float32 [N][M] array (tiles through LDS).
+hipError_t launch_transpose_f32(const float* in, float* out, int64_t N, int64_t M, hipStream_t st);
 
 // Blocked workspace (rows rows in blocks of rb) -> row-major out, times scale;
 // complex64 or, with out_f32, the real parts.

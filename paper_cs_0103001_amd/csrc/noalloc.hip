@@ -43,11 +43,9 @@ int scratch_ptr(int dev, void** out) {
   return FFT_OK;
 }
 
-// Bytes of workspace fft2d_filter actually touches on this plan: one chunk's
-// blocked intermediate (the passes run chunk by chunk over the same region),
-// or, on a padded plan, the whole layout including the padded input and output.
-size_t filter_need(const fftmi_plan* p) {
-  if (p->padded) return p->ws_bytes;
+// Bytes of one chunk's blocked intermediate (the passes run chunk by chunk
+// over the same region).
+size_t chunk_bytes(const fftmi_plan* p) {
   const int64_t chunk = std::min<int64_t>(std::max<int64_t>(p->chunk, 1), std::max<int64_t>(p->batch, 1));
   return (size_t)chunk * (size_t)p->img * sizeof(float2);
 }
@@ -61,11 +59,18 @@ extern "C" int fft2d_filter_noalloc(fft_plan_t p, const void* in, void* out, con
   int rc = plan_check(p, &dev);
   if (rc != FFT_OK) return rc;
   if (p->batch == 0) return FFT_OK;
-  if (filter_need(p) > (size_t)FFT_NOALLOC_SCRATCH_BYTES) return FFT_ERR_SCRATCH;
+  // what the filter touches: one chunk's intermediate, then (a tensor mask on
+  // a plan with long columns) the mask's transposed copy; a padded plan's
+  // whole workspace layout (its transposed mask region included)
+  const bool maskt = mask && mask->kind == FFT_MASK_TENSOR_F32 && maskt_bytes(p) > 0;
+  const size_t mt_off = (chunk_bytes(p) + 255) & ~(size_t)255;
+  const size_t need = p->padded ? p->ws_bytes : (maskt ? mt_off + maskt_bytes(p) : chunk_bytes(p));
+  if (need > (size_t)FFT_NOALLOC_SCRATCH_BYTES) return FFT_ERR_SCRATCH;
   void* ws = nullptr;
   rc = scratch_ptr(dev, &ws);
   if (rc != FFT_OK) return rc;
   // Nothing in the scratch needs clearing: the row pass (or the padding
   // kernel) writes every element the later passes read.
-  return filter_run(p, in, out, mask, nullptr, ws, stream, 7, p->chunk);
+  float* mt = maskt && !p->padded ? reinterpret_cast<float*>(static_cast<char*>(ws) + mt_off) : nullptr;
+  return filter_run(p, in, out, mask, nullptr, ws, stream, 7, p->chunk, mt);
 }

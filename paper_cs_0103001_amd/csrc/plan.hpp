@@ -58,6 +58,9 @@ struct fftmi_plan {
   // offsets of their partial sums and of the fused MSE forward's per-tile sums
   int grad_groups = 1;
   size_t part_off = 0, loss_off = 0, loss_mid_off = 0;
+  // rank 2 with columns of 2048 points or more (tiles of one or two columns):
+  // workspace offset of a transposed copy of a tensor mask (0: none)
+  size_t maskt_off = 0;
   fftmi::RaggedState* ragged = nullptr;
   // fft_plan_tree: log2 of the number of processes, Table 2's factors Z[0 .. N/2)
   int tree_l = 0;
@@ -103,8 +106,12 @@ void destroy_tree_state(fftmi_plan* p);
 // column pass, bit 2 inverse row pass), run over the batch in chunks of
 // `chunk` images when all three are selected, with `workspace` holding one
 // chunk's blocked intermediate.
+// maskt: where a tensor mask's transposed copy goes (nullptr: the plan's
+// workspace region at maskt_off); used only when the plan has that region.
 int filter_run(fftmi_plan* p, const void* in, void* out, const fft_mask* mask, void* spectrum, void* workspace,
-               void* stream, int stages, int64_t chunk);
+               void* stream, int stages, int64_t chunk, float* maskt = nullptr);
+// Bytes of the transposed tensor mask (0 when the plan reads masks as given).
+size_t maskt_bytes(const fftmi_plan* p);
 
 struct MaskArgs;
 // The plan is live and its device is current (FFT_OK, FFT_ERR_ARG, FFT_ERR_STATE, FFT_ERR_HIP).

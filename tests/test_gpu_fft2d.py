@@ -61,7 +61,8 @@ def test_small_256_gaussian_workload():
 @pytest.mark.parametrize("N,M,kind", [(512, 512, "butterworth"), (64, 256, "butterworth"), (256, 64, "gaussian"),
                                       (512, 512, "disc"), (32, 32, "tensor"), (1024, 1024, "tensor"),
                                       (16, 16, "gaussian"), (4, 8, "butterworth"), (1, 1, "gaussian"),
-                                      (32, 16384, "butterworth"), (16384, 32, "gaussian")])
+                                      (32, 16384, "butterworth"), (16384, 32, "gaussian"),
+                                      (2048, 512, "tensor"), (4096, 64, "tensor")])
 @pytest.mark.parametrize("complex_in", [False, True])
 def test_filter_kinds_vs_oracle(N, M, kind, complex_in):
     api = _api()
@@ -201,3 +202,36 @@ def test_non_finite_input_propagates(bad):
         assert rel_l2(y[b], oracle.filter2(x[b], m), 2) < TOL
     yr = to_host(api.fft2d_filter(to_dev(x), None, real_even=True, real_output=True))
     assert not np.isfinite(yr[1]).any() and np.isfinite(yr[0]).all() and np.isfinite(yr[2]).all()
+
+
+def test_tensor_mask_long_columns_stages_and_fused_mse():
+    """Tensor masks on plans with columns of 2048 points or more (read from a
+    transposed copy made per call): the three stages run one by one equal the
+    whole filter bit for bit, and the fused filter + MSE loss and gradient
+    match the oracle."""
+    import torch
+    from paper_cs_0103001_amd import _binding as B
+    from paper_cs_0103001_amd import api
+    from paper_cs_0103001_amd.autograd import fft_filter_mse
+    N, M, Bn = 4096, 64, 2
+    x = np.stack([synth.star_field(N, M, 800, 1.5, (33, b)) for b in range(Bn)])
+    mask = np.random.default_rng(41).uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    xd, md = to_dev(x), to_dev(mask)
+    announce("tensor mask %dx%d stages" % (N, M))
+    whole = to_host(api.fft2d_filter(xd, md))
+    assert rel_l2(whole, oracle.filter2(x, mask.astype(np.float64)), 2) < TOL
+    plan = api.get_plan(2, (N, M), Bn, B.FFT_IN_REAL_F32, xd.device)
+    ws = plan.workspace()
+    out = torch.empty((Bn, N, M), dtype=torch.complex64, device="cuda")
+    mk = B.make_mask("tensor", data_ptr=md.data_ptr())
+    for s_ in (0, 1, 2):
+        B.fft2d_filter_stage(plan.h, s_, api._ptr(xd), api._ptr(out), mk, api._ptr(ws), api._stream(xd.device))
+    assert np.array_equal(to_host(out).view(np.uint32), whole.view(np.uint32))
+    announce("tensor mask %dx%d fused mse" % (N, M))
+    clean = (x - np.float32(3.0)).astype(np.float32)
+    m = md.clone().requires_grad_(True)
+    L = fft_filter_mse(xd, to_dev(clean), m)
+    L.backward()
+    _, L_ref, g_ref = oracle.loss_grad(x, clean, mask)
+    assert abs(float(L.detach()) - L_ref) / L_ref < 1e-5
+    assert rel_l2(to_host(m.grad), g_ref, 2) < TOL

@@ -99,3 +99,31 @@ def test_noalloc_refuses_plans_beyond_scratch():
         assert B.lib().fft2d_filter_noalloc(h, None, None, None, st) == B.FFT_ERR_STATE
     finally:
         B.fft_plan_destroy(h)
+
+
+def test_noalloc_tensor_mask_long_columns():
+    """A tensor mask on a plan with 2048-point columns: its transposed copy
+    also lives in the scratch (2048 x 1024: 16 MiB intermediate + 8 MiB);
+    4096 x 4096 with a tensor mask needs 192 MiB and is refused."""
+    import torch
+    from paper_cs_0103001_amd import _binding as B
+    announce("noalloc tensor mask 2048x1024")
+    img = np.stack([synth.star_field(2048, 1024, 6000, 1.5, seed=12)])
+    mask = np.random.default_rng(13).uniform(0.2, 1.2, (2048, 1024)).astype(np.float32)
+    md = to_dev(mask)
+    mk = B.make_mask("tensor", data_ptr=md.data_ptr())
+    a, b = _run(B, torch, img, (2048, 1024), B.FFT_IN_REAL_F32, mk)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    assert rel_l2(b[0], oracle.filter2(img[0], mask.astype(np.float64)), 2) < TOL
+    h = B.fft_plan(2, (4096, 4096), 1, B.FFT_IN_REAL_F32)
+    try:
+        st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        m4 = torch.ones((4096, 4096), dtype=torch.float32, device="cuda")
+        x = torch.zeros((4096, 4096), dtype=torch.float32, device="cuda")
+        out = torch.zeros((4096, 4096), dtype=torch.complex64, device="cuda")
+        mk4 = B.make_mask("tensor", data_ptr=m4.data_ptr())
+        rc = B.lib().fft2d_filter_noalloc(h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.byref(mk4), st)
+        assert rc == B.FFT_ERR_SCRATCH
+    finally:
+        B.fft_plan_destroy(h)
