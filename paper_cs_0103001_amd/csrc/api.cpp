@@ -419,6 +419,7 @@ int fft_plan_padded(fft_plan_t* out, const int64_t* dims0, int64_t batch, uint32
 }
 
 int fft2d_spectrum(fft_plan_t p, const void* in, float* magnitude, void* workspace, void* stream) {
+  TraceRange tr("fft2d_spectrum");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
   if (p->half) return FFT_ERR_UNSUPPORTED;
@@ -476,6 +477,7 @@ int fft_spectrum_size(fft_plan_t plan, size_t* bytes) {
 }
 
 int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direction, void* stream) {
+  TraceRange tr("fft_exec");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (direction != FFT_FORWARD && direction != FFT_INVERSE && direction != FFT_ADJ_FORWARD &&
       direction != FFT_ADJ_INVERSE)
@@ -628,17 +630,20 @@ int fftmi::filter_run(fftmi_plan* p, const void* in, void* out, const fft_mask* 
 extern "C" {
 
 int fft2d_filter(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* workspace, void* stream) {
+  TraceRange tr("fft2d_filter");
   return filter_run(p, in, out, mask, nullptr, workspace, stream, 7, plan_live(p) ? p->chunk : 1);
 }
 
 int fft2d_filter_stage(fft_plan_t p, int stage, const void* in, void* out, const fft_mask* mask, void* workspace,
                        void* stream) {
+  TraceRange tr("fft2d_filter_stage");
   if (stage < 0 || stage > 2) return FFT_ERR_ARG;
   return filter_run(p, in, out, mask, nullptr, workspace, stream, 1 << stage, 1);
 }
 
 int fft2d_filter_save(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* spectrum,
                       void* workspace, void* stream) {
+  TraceRange tr("fft2d_filter_save");
   if (!spectrum) return FFT_ERR_ARG;
   return filter_run(p, in, out, mask, spectrum, workspace, stream, 7, plan_live(p) ? p->chunk : 1);
 }
@@ -695,17 +700,20 @@ static int grad_impl(fftmi_plan* p, const void* in, const void* in2, const void*
 
 int fft2d_filter_mask_grad(fft_plan_t p, const void* grad_y, const void* spectrum, float* grad_mask,
                            void* workspace, void* stream) {
+  TraceRange tr("fft2d_filter_mask_grad");
   return grad_impl(p, grad_y, nullptr, spectrum, nullptr, 1.0f, grad_mask, workspace, stream);
 }
 
 int fft2d_filter_mse_grad(fft_plan_t p, const void* x, const void* c, const void* spectrum, const float* mask,
                           float weight, float* grad_mask, void* workspace, void* stream) {
+  TraceRange tr("fft2d_filter_mse_grad");
   if (!mask && plan_live(p) && p->batch > 0) return FFT_ERR_ARG;
   return grad_impl(p, x, c, spectrum, mask, weight, grad_mask, workspace, stream);
 }
 
 int fft2d_filter_mse(fft_plan_t p, const float* x, const float* c, const float* mask, float weight, void* spectrum,
                      float* loss, void* workspace, void* stream) {
+  TraceRange tr("fft2d_filter_mse");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
   if (p->padded || p->half || !(p->flags & FFT_IN_REAL_F32) || p->rb < 2) return FFT_ERR_UNSUPPORTED;

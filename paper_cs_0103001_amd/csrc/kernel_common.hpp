@@ -150,6 +150,15 @@ template <int L>
 using ColsCfg = XCfg<L, FFTMI_TWM_COLS, FFTMI_SPLIT_COLS != 0>;
 template <int L>
 using RowsOutCfg = XCfg<L, FFTMI_TWM_ROWS_OUT, FFTMI_SPLIT_ROWS_OUT != 0>;
+// The mask-gradient column pass (see k_cols_grad).
+#ifndef FFTMI_TWM_GRAD
+#define FFTMI_TWM_GRAD FFTMI_TWM
+#endif
+#ifndef FFTMI_SPLIT_GRAD
+#define FFTMI_SPLIT_GRAD FFTMI_SPLIT_X
+#endif
+template <int L>
+using GradCfg = XCfg<L, FFTMI_TWM_GRAD, FFTMI_SPLIT_GRAD != 0>;
 // 1D transforms in one pass (up to 2^14 points): mixed twiddles at every
 // length, since these kernels run without a prefetch buffer (2^13 points:
 // 4.1 TB/s against 3.1 with the global tables and a prefetch).

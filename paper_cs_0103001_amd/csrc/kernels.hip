@@ -769,6 +769,9 @@ __global__ __launch_bounds__(256) void k_unblock_mag(const float2* __restrict__ 
 // where T_b is the unscaled transform.  Partials of consecutive groups are
 // added in group order by k_sum_groups, so the result does not depend on the
 // launch shape's timing.
+#ifndef FFTMI_GRAD_XFIRST
+#define FFTMI_GRAD_XFIRST 0
+#endif
 template <int L, bool MT>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __restrict__ ws, const float2* __restrict__ save,
                                                             const float* __restrict__ mask, float* __restrict__ part,
@@ -777,11 +780,12 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
                                                             int ntiles, float w_lin, float w_sq,
                                                             const float2* __restrict__ tws) {
   using S = Shape<L>;
+  using C = GradCfg<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const ColLanes ln = col_lanes(threadIdx.x, rb, w);
-  const Twiddles<L> twd(tws, ln.j);
+  const Twiddles<L, C::TWM> twd(tws, ln.j);
   const float2* tw = twd.ptr();
-  char* x = regions<L>() + ln.c * lds_region_bytes(L, w);
+  char* x = regions<L, C>() + ln.c * C::region(w);
   const unsigned qs = (unsigned)(TPT / rb) * bs;        // blocked layout, rows j + q*TPT
   const unsigned qs_out = (unsigned)(TPT * M);           // row-major mask and partial sums
   const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
@@ -795,28 +799,32 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
     float acc[E], acc2[E];
 #pragma unroll
     for (int q = 0; q < E; ++q) acc[q] = acc2[q] = 0.f;
-    // one image at a time: the residual's loads, its transform, then the
-    // saved spectrum's loads and the products.  No next-image prefetch: the
-    // spectrum loads would wait behind it (loads complete in order), and
-    // without it the kernel fits four workgroups per CU.
+    // one image at a time: the residual's loads, its transform, and the
+    // saved spectrum's loads and products
     for (int bi = b0; bi < b1; ++bi) {
-      float2 a[E];
+      float2 a[E], X[E];
       const float2* b = ws + bi * plane + ct * w * rb;
       const float2* xs = save + bi * plane + ct * w * rb;
       {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
         for (int q = 0; q < E; ++q) a[q] = ld(b, f_lane + q * qs);
+        if constexpr (FFTMI_GRAD_XFIRST) {
+          // the spectrum's loads in flight during the transform
+#pragma unroll
+          for (int q = 0; q < E; ++q) X[q] = ld(xs, f_lane + q * qs);
+        }
       }
-      fft_reg<L, false, S::TWM>(a, ln.j, x, tw);
-      {
+      fft_reg<L, false, C::TWM, C::SPLIT>(a, ln.j, x, tw);
+      if constexpr (!FFTMI_GRAD_XFIRST) {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-          const float2 X = ld(xs, f_lane + q * qs);
-          acc[q] = fmaf(X.x, a[q].x, fmaf(X.y, a[q].y, acc[q]));
-          if constexpr (MT) acc2[q] = fmaf(X.x, X.x, fmaf(X.y, X.y, acc2[q]));
-        }
+        for (int q = 0; q < E; ++q) X[q] = ld(xs, f_lane + q * qs);
+      }
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        acc[q] = fmaf(X[q].x, a[q].x, fmaf(X[q].y, a[q].y, acc[q]));
+        if constexpr (MT) acc2[q] = fmaf(X[q].x, X[q].x, fmaf(X[q].y, X[q].y, acc2[q]));
       }
     }
     const unsigned f_lane_out = fresh(lane_out);
@@ -1249,16 +1257,17 @@ struct ColsGrad {
   static hipError_t run(const float2* ws, const float2* save, const float* mask, float* part, int64_t nimg,
                         int groups, int M, int rb, unsigned bs, int w, float w_lin, float w_sq, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
-    const int lds = tw_bytes<L>() + w * lds_region_bytes(L, w);
+    using C = GradCfg<L>;
+    const int lds = C::TWB + w * C::region(w);
     const int ctiles = M / w;
     const int per_group = (int)((nimg + groups - 1) / groups);
     const int64_t ntiles = (int64_t)groups * ctiles;
     const int lt = ilog2c(ctiles);
     if (mask)
       return go(k_cols_grad<L, true>, ntiles, w * TPT, lds, lc.stream, ws, save, mask, part, (int)nimg, per_group,
-                M, rb, bs, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
+                M, rb, bs, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L, C>(lc));
     return go(k_cols_grad<L, false>, ntiles, w * TPT, lds, lc.stream, ws, save, mask, part, (int)nimg, per_group, M,
-              rb, bs, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L>(lc));
+              rb, bs, w, lt, (int)ntiles, w_lin, w_sq, twiddle_src<L, C>(lc));
   }
 };
 

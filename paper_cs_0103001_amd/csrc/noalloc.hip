@@ -53,6 +53,7 @@ size_t chunk_bytes(const fftmi_plan* p) {
 }  // namespace
 
 extern "C" int fft2d_filter_noalloc(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* stream) {
+  TraceRange tr("fft2d_filter_noalloc");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
   int dev = -1;

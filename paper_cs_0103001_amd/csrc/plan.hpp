@@ -5,6 +5,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <string>
 
 #include "../../include/fftmi.h"
@@ -15,6 +17,16 @@ struct DevTables;     // per-device twiddle tables (api.cpp)
 struct RaggedState;   // ragged work list, device buffers and graph (ragged.cpp)
 
 constexpr uint32_t kPlanMagic = 0x46465449u;
+
+// A rocTX range around one C-ABI call that enqueues device work: it names the
+// call in a profiler's marker trace (rocprofv3 --marker-trace) and costs a
+// function call when no profiler listens.
+struct TraceRange {
+  explicit TraceRange(const char* name) { roctxRangePush(name); }
+  ~TraceRange() { roctxRangePop(); }
+  TraceRange(const TraceRange&) = delete;
+  TraceRange& operator=(const TraceRange&) = delete;
+};
 
 extern thread_local std::string g_err_text;
 int hip_fail(hipError_t e);

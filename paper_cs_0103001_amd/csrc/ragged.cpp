@@ -491,6 +491,7 @@ int fft_plan_ragged(fft_plan_t* out, int64_t count, const int64_t* sizes, uint32
 }
 
 int fft2d_filter_ragged(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* workspace, void* stream) {
+  TraceRange tr("fft2d_filter_ragged");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 3 || !p->ragged) return FFT_ERR_STATE;
   RaggedState* r = p->ragged;
@@ -526,6 +527,7 @@ int fft2d_filter_ragged(fft_plan_t p, const void* in, void* out, const fft_mask*
 }
 
 int fft_plan_tune(fft_plan_t p, const void* in, void* out, const fft_mask* mask, void* workspace, void* stream) {
+  TraceRange tr("fft_plan_tune");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 3 || !p->ragged) return FFT_ERR_UNSUPPORTED;
   if (p->batch == 0) return FFT_OK;

@@ -225,6 +225,7 @@ int fft_plan_tree(fft_plan_t* out, int64_t n, int log2_procs, uint32_t flags) {
 
 int fft_tree_exec(fft_plan_t p, const void* in, void* out, void* workspace, fft_tree_stats* stats,
                   int64_t spin_limit, void* stream) {
+  TraceRange tr("fft_tree_exec");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 4) return FFT_ERR_STATE;
   if (!in || !out || !stats || in == out || spin_limit < 1) return FFT_ERR_ARG;

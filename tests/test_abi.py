@@ -139,3 +139,14 @@ def test_learnable_mask_wrappers_validate_before_any_launch():
         api.mse_grad(x, x.double(), torch.zeros(1, dtype=torch.uint8), mask, 1.0)
     with pytest.raises(ValueError):
         api.mask_grad(torch.zeros((16,), dtype=torch.complex64), torch.zeros(1, dtype=torch.uint8))
+
+
+def test_entry_points_open_roctx_ranges():
+    """The library names each entry point's device work with rocTX ranges
+    (rocprofv3 --marker-trace shows them)."""
+    import shutil
+    import subprocess
+    if not shutil.which("nm"):
+        pytest.skip("nm not found")
+    out = subprocess.run(["nm", "-D", B.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out

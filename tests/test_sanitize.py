@@ -83,7 +83,8 @@ def test_abi_validation_under_asan_ubsan(tmp_path):
           "-c", os.path.join(HERE, "sanitize", "abi_checks.c"), "-o", drv])
     exe = str(tmp_path / "abi_checks")
     _run([CLANGXX, "-fsanitize=address,undefined", "-o", exe, drv, *objs, *kobjs,
-          "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(ROCM, "lib")])
+          "-L" + os.path.join(ROCM, "lib"), "-lamdhip64", "-lrocprofiler-sdk-roctx",
+          "-Wl,-rpath," + os.path.join(ROCM, "lib")])
     # no GPU: plan creation past the argument checks reports FFT_ERR_HIP
     r = _run([exe], env=SAN_ENV, timeout=120)
     assert "0 failure(s)" in r.stdout
