@@ -341,6 +341,10 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       // the intermediate [N2][N1] rows get a padded stride, so that the
       // second pass's column reads do not all land on the same channels
       p->fs_rs = (1 << p->log_n1) + fourstep_pad(p->log_n1);
+      // pass two with non-temporal loads and stores up to 2^20 points
+      // (+3-7% there, 4-10% slower at 2^21 and 2^22); FFTMI_FS_NT=0/1 forces
+      p->fs_nt = p->log_n <= 20;
+      if (const char* e = std::getenv("FFTMI_FS_NT")) p->fs_nt = std::atoi(e) != 0;
       p->ws_bytes = (size_t)batch * (size_t)(1 << p->log_n2) * (size_t)p->fs_rs * sizeof(float2);
     }
   } else {
@@ -513,11 +517,11 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
     const int64_t wsb = (int64_t)n2 * p->fs_rs;
     Launch l1 = launch_for(st, p->tables, p->log_n1);
     e = launch_cols_strided(p->log_n1, inv_tw, true, static_cast<const float2*>(in), ws, p->batch, n2, p->w1, 1.0f,
-                            p->tw_fs, p->n, n2, wsb, p->fs_rs, l1);
+                            p->tw_fs, p->n, n2, wsb, p->fs_rs, false, l1);
     if (e != hipSuccess) return hip_fail(e);
     Launch l2 = launch_for(st, p->tables, p->log_n2);
     e = launch_cols_strided(p->log_n2, inv_tw, false, ws, static_cast<float2*>(out), p->batch, n1, p->w2, scale,
-                            nullptr, wsb, p->fs_rs, p->n, n1, l2);
+                            nullptr, wsb, p->fs_rs, p->n, n1, p->fs_nt, l2);
     return e == hipSuccess ? FFT_OK : hip_fail(e);
   }
 

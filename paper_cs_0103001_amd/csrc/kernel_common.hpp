@@ -44,6 +44,28 @@ __device__ __forceinline__ char* lds_base() {
 #define FFTMI_PF_ROWS_1D 0
 #endif
 enum { kPassRowsIn = 0, kPassCols = 1, kPassRowsOut = 2, kPassRows1D = 3 };
+// Non-temporal accesses per kernel family, as bit masks, measured per
+// family.  One-pass 1D rows: 1 loads, 2 stores (stores only: 2^10..2^14 at
+// 6.4-6.6 / 5.7 / 4.7 TB/s against 5.0 / 4.3 / 3.9 without; loads too: less).
+// Ragged passes: 1 the first row pass's loads, 2 the column pass's loads, 4
+// the last row pass's loads (none: each was slower).  The four-step pass two
+// chooses at plan creation.
+#ifndef FFTMI_NT_1D
+#define FFTMI_NT_1D 2
+#endif
+#ifndef FFTMI_NT_RAGGED
+#define FFTMI_NT_RAGGED 0
+#endif
+// Stores with the non-temporal hint: the saved spectrum of the fused MSE
+// forward (FFTMI_NT_SAVE: read back only by the backward pass, after the
+// whole batch), the residual spectrum rows of the mask gradient
+// (FFTMI_NT_DIFF: slower).
+#ifndef FFTMI_NT_SAVE
+#define FFTMI_NT_SAVE 1
+#endif
+#ifndef FFTMI_NT_DIFF
+#define FFTMI_NT_DIFF 0
+#endif
 // Transforms of 2^14 points take 1024-thread workgroups, whose threads have
 // at most 128 VGPRs: too few for a second tile, so they never prefetch.
 template <int L, int PASS>
@@ -208,12 +230,45 @@ __device__ __forceinline__ float2 ld_nt(const float2* __restrict__ base, unsigne
   const fftmi_f2v v = __builtin_nontemporal_load(reinterpret_cast<const fftmi_f2v*>(base + off));
   return make_float2(v.x, v.y);
 }
+typedef float fftmi_f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4* __restrict__ base, unsigned off) {
+  const fftmi_f4v v = __builtin_nontemporal_load(reinterpret_cast<const fftmi_f4v*>(base + off));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+// A load with the non-temporal hint when NT: for data that a pass reads once
+// and that is larger than the memory-side cache (a batch's intermediate, the
+// saved spectrum), so it does not evict what is still to be read or written.
+template <bool NT, typename T>
+__device__ __forceinline__ T ldh(const T* __restrict__ base, unsigned off) {
+  if constexpr (NT) {
+    return ld_nt(base, off);
+  } else {
+    return __ldg(base + off);
+  }
+}
 __device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void st_nt(float2* p, float2 v) {
   fftmi_f2v w;
   w.x = v.x;
   w.y = v.y;
   __builtin_nontemporal_store(w, reinterpret_cast<fftmi_f2v*>(p));
+}
+__device__ __forceinline__ void st_nt(float4* p, float4 v) {
+  fftmi_f4v w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  __builtin_nontemporal_store(w, reinterpret_cast<fftmi_f4v*>(p));
+}
+// A store with the non-temporal hint when NT.
+template <bool NT, typename T>
+__device__ __forceinline__ void sth(T* p, T v) {
+  if constexpr (NT) {
+    st_nt(p, v);
+  } else {
+    *p = v;
+  }
 }
 
 // Buffer-resource access to one image of the blocked workspace.  The image's
@@ -232,8 +287,11 @@ struct BlkBuf {
   __device__ __forceinline__ float2 ld(unsigned voff, unsigned soff) const {
     return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   }
+  // NT: the non-temporal cache policy (bit 1 of the instruction's cache
+  // policy operand on this architecture)
+  template <bool NT = false>
   __device__ __forceinline__ void st(float2 v, unsigned voff, unsigned soff) const {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(fftmi_i2v, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(fftmi_i2v, v), r, voff, soff, NT ? 2 : 0);
   }
 };
 

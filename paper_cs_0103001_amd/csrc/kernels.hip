@@ -53,14 +53,14 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
       {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) d[q] = make_float2(ok ? ld(b, f_lane + q * TPT) : 0.f, 0.f);
+        for (int q = 0; q < E; ++q) d[q] = make_float2(ok ? ldh<(FFTMI_NT_1D & 1) != 0>(b, f_lane + q * TPT) : 0.f, 0.f);
       }
     } else {
       const float2* b = static_cast<const float2*>(in) + (int64_t)tile * tpw * L;
       {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) d[q] = ok ? ld(b, f_lane + q * TPT) : make_float2(0.f, 0.f);
+        for (int q = 0; q < E; ++q) d[q] = ok ? ldh<(FFTMI_NT_1D & 1) != 0>(b, f_lane + q * TPT) : make_float2(0.f, 0.f);
       }
     }
   };
@@ -83,14 +83,14 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_rm(const void* __restrict
         {
           const unsigned f_lane = fresh(lane);
 #pragma unroll
-          for (int q = 0; q < E; ++q) b[f_lane + q * TPT] = a[q].x * scale;
+          for (int q = 0; q < E; ++q) sth<(FFTMI_NT_1D & 2) != 0>(b + f_lane + q * TPT, a[q].x * scale);
         }
       } else {
         float2* b = static_cast<float2*>(out) + (int64_t)tile * tpw * L;
         {
           const unsigned f_lane = fresh(lane);
 #pragma unroll
-          for (int q = 0; q < E; ++q) b[f_lane + q * TPT] = cscale(a[q], scale);
+          for (int q = 0; q < E; ++q) sth<(FFTMI_NT_1D & 2) != 0>(b + f_lane + q * TPT, cscale(a[q], scale));
         }
       }
     }
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
         const int v = v0 + i * TPT, vm = (L - v) & (L - 1);
         const float zi = reinterpret_cast<const float*>(xs)[lds_pad(v)];
         const float zmi = reinterpret_cast<const float*>(xs)[lds_pad(vm)];
-        dst[lo + i * TPT * np] = make_float4(ax[i], h * (zi - zmi), h * (zi + zmi), by[i]);
+        sth<DIFF && (FFTMI_NT_DIFF != 0)>(dst + lo + i * TPT * np, make_float4(ax[i], h * (zi - zmi), h * (zi + zmi), by[i]));
       }
     } else {
       lds_barrier();
@@ -210,7 +210,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_rows_to_blk_pair(const float* 
           const float2 zh = reinterpret_cast<const float2*>(xs)[lds_pad(L / 2)];
           o = make_float4(2.f * h * z.x, 2.f * h * zh.x, 2.f * h * z.y, 2.f * h * zh.y);
         }
-        dst[lo + i * TPT * np] = o;
+        sth<DIFF && (FFTMI_NT_DIFF != 0)>(dst + lo + i * TPT * np, o);
       }
     }
     if constexpr (Prefetch<L, kPassRowsIn>::on) {
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_filter(float2* __restrict
     if (save) {
       const BlkBuf sb(save + (int64_t)(t >> ltiles) * img, (uint64_t)img * 8u);
 #pragma unroll
-      for (int q = 0; q < E; ++q) sb.st(a[q], vlane, toff + q * qs8);
+      for (int q = 0; q < E; ++q) sb.template st<FFTMI_NT_SAVE != 0>(a[q], vlane, toff + q * qs8);
     }
     const int mfreq = HALF ? 2 * M : M;  // columns of the frequency grid
     if constexpr (HALF) {
@@ -772,6 +772,9 @@ __global__ __launch_bounds__(256) void k_unblock_mag(const float2* __restrict__ 
 #ifndef FFTMI_GRAD_XFIRST
 #define FFTMI_GRAD_XFIRST 0
 #endif
+#ifndef FFTMI_GRAD_NT
+#define FFTMI_GRAD_NT 1
+#endif
 template <int L, bool MT>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __restrict__ ws, const float2* __restrict__ save,
                                                             const float* __restrict__ mask, float* __restrict__ part,
@@ -792,6 +795,10 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
   const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
   const int64_t plane = (int64_t)(L / rb) * bs;
   const int tmask = (1 << ltiles) - 1;
+  // the residual and the saved spectrum are each read once: non-temporal
+  auto gl = [](const float2* base, unsigned off) __attribute__((always_inline)) {
+    return ldh<FFTMI_GRAD_NT != 0>(base, off);
+  };
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
     const int g = t >> ltiles, ct = t & tmask;
@@ -808,18 +815,18 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
       {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) a[q] = ld(b, f_lane + q * qs);
+        for (int q = 0; q < E; ++q) a[q] = gl(b, f_lane + q * qs);
         if constexpr (FFTMI_GRAD_XFIRST) {
           // the spectrum's loads in flight during the transform
 #pragma unroll
-          for (int q = 0; q < E; ++q) X[q] = ld(xs, f_lane + q * qs);
+          for (int q = 0; q < E; ++q) X[q] = gl(xs, f_lane + q * qs);
         }
       }
       fft_reg<L, false, C::TWM, C::SPLIT>(a, ln.j, x, tw);
       if constexpr (!FFTMI_GRAD_XFIRST) {
         const unsigned f_lane = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) X[q] = ld(xs, f_lane + q * qs);
+        for (int q = 0; q < E; ++q) X[q] = gl(xs, f_lane + q * qs);
       }
 #pragma unroll
       for (int q = 0; q < E; ++q) {
@@ -867,10 +874,13 @@ __global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ p
 // WIDE: tiles of up to 1024 threads (twice the columns of the 512-thread
 // tiles, so twice the contiguous bytes per row), with no prefetch, as the
 // 128 VGPRs a thread then has leave no room for a second tile.
+// nt (pass two): non-temporal loads of the intermediate and stores of the
+// result.
 template <int L, bool INV, bool WIDE, bool TT>
 __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
     const float2* __restrict__ in, float2* __restrict__ out, int C, int w, int ltiles, int ntiles, float scale,
-    const float2* __restrict__ tfs, const float2* __restrict__ tws, int64_t ib, int irs, int64_t ob, int ors) {
+    const float2* __restrict__ tfs, const float2* __restrict__ tws, int64_t ib, int irs, int64_t ob, int ors,
+    int nt) {
   using S = Shape<L>;
   constexpr int E = S::E, TPT = S::TPT;
   const int lw = ilog2_pow2(w);
@@ -894,8 +904,11 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
   auto ctile_of = [&](int t) __attribute__((always_inline)) { return TT ? t / nent : t & tmask; };
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
     const float2* b = in + (int64_t)entry_of(t) * ib + ctile_of(t) * w;
-    {
-      const unsigned f_lane = fresh(lane);
+    const unsigned f_lane = fresh(lane);
+    if (!TT && nt) {
+#pragma unroll
+      for (int q = 0; q < E; ++q) d[q] = ld_nt(b, f_lane + q * qs);
+    } else {
 #pragma unroll
       for (int q = 0; q < E; ++q) d[q] = ld(b, f_lane + q * qs);
     }
@@ -965,8 +978,13 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
       {
         const unsigned f_lane = fresh((unsigned)(j * ors + c));
         const unsigned oqs = (unsigned)(TPT * ors);
+        if (nt) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) b[f_lane + q * oqs] = cscale(a[q], scale);
+          for (int q = 0; q < E; ++q) st_nt(b + f_lane + q * oqs, cscale(a[q], scale));
+        } else {
+#pragma unroll
+          for (int q = 0; q < E; ++q) b[f_lane + q * oqs] = cscale(a[q], scale);
+        }
       }
     }
     if constexpr (PF) {
@@ -1275,21 +1293,21 @@ template <int LG>
 struct ColsStrided {
   template <bool INV, bool WIDE, bool TT>
   static hipError_t go_one(const float2* in, float2* out, int64_t ntiles, int w, int lds, int C, int lt, float scale,
-                           const float2* tfs, const float2* tw, int64_t ib, int irs, int64_t ob, int ors,
+                           const float2* tfs, const float2* tw, int64_t ib, int irs, int64_t ob, int ors, int nt,
                            const Launch& lc) {
     constexpr int TPT = threads_per_transform(1 << LG);
     return go(k_cols_strided<1 << LG, INV, WIDE, TT>, ntiles, w * TPT, lds, lc.stream, in, out, C, w, lt,
-              (int)ntiles, scale, tfs, tw, ib, irs, ob, ors);
+              (int)ntiles, scale, tfs, tw, ib, irs, ob, ors, nt);
   }
   template <bool INV, bool WIDE>
   static hipError_t go_tt(bool twt, const float2* in, float2* out, int64_t ntiles, int w, int lds, int C, int lt,
                           float scale, const float2* tfs, const float2* tw, int64_t ib, int irs, int64_t ob, int ors,
-                          const Launch& lc) {
-    return twt ? go_one<INV, WIDE, true>(in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc)
-               : go_one<INV, WIDE, false>(in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc);
+                          int nt, const Launch& lc) {
+    return twt ? go_one<INV, WIDE, true>(in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, nt, lc)
+               : go_one<INV, WIDE, false>(in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, nt, lc);
   }
   static hipError_t run(bool inv, bool twt, const float2* in, float2* out, int64_t batch, int C, int w, float scale,
-                        const float2* tfs, int64_t ib, int irs, int64_t ob, int ors, const Launch& lc) {
+                        const float2* tfs, int64_t ib, int irs, int64_t ob, int ors, bool nt, const Launch& lc) {
     // the four-step splits use column lengths 2^7 .. 2^12 only
     if constexpr (LG < 7 || LG > 12) {
       return hipErrorInvalidValue;
@@ -1303,10 +1321,10 @@ struct ColsStrided {
       if (w * TPT > 1024) return hipErrorInvalidValue;
       const bool wide = w * TPT > max_block<L>();
       if (inv)
-        return wide ? go_tt<true, true>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc)
-                    : go_tt<true, false>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc);
-      return wide ? go_tt<false, true>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc)
-                  : go_tt<false, false>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, lc);
+        return wide ? go_tt<true, true>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, nt, lc)
+                    : go_tt<true, false>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, nt, lc);
+      return wide ? go_tt<false, true>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, nt, lc)
+                  : go_tt<false, false>(twt, in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, nt, lc);
     }
   }
 };
@@ -1347,7 +1365,7 @@ struct ColsStrided {
 #define FFTMI_CASE_ColsStrided(K) \
   case K:                         \
     return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_fs, in_bstride, in_rstride, \
-                               out_bstride, out_rstride, lc);
+                               out_bstride, out_rstride, nt, lc);
 
 hipError_t launch_rows_rm(int log2L, bool inv, const void* in, bool in_f32, void* out, bool out_f32, int64_t rows,
                           float scale, const Launch& lc) {
@@ -1516,7 +1534,7 @@ hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int grou
 
 hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,
                                int64_t batch, int C, int w, float scale, const float2* tw_fs, int64_t in_bstride,
-                               int in_rstride, int64_t out_bstride, int out_rstride, const Launch& lc) {
+                               int in_rstride, int64_t out_bstride, int out_rstride, bool nt, const Launch& lc) {
   FFTMI_DISPATCH(ColsStrided, log2L)
 }
 

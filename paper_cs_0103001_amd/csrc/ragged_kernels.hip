@@ -35,6 +35,8 @@ namespace fftmi {
 namespace {
 
 constexpr int kRaggedMaxBlock = 512;
+constexpr bool kNtRowsFwd = (FFTMI_NT_RAGGED & 1) != 0, kNtCols = (FFTMI_NT_RAGGED & 2) != 0,
+               kNtRowsInv = (FFTMI_NT_RAGGED & 4) != 0;
 // LDS bytes reserved for the short stage tables (the largest, 2048 points:
 // 15 x 16 entries)
 constexpr int kRgTwBytes = 2048;
@@ -67,7 +69,7 @@ __device__ __forceinline__ void rg_rows_fwd(const float2* __restrict__ in, float
   const float2* src = in + im.off + (int64_t)(ok ? u : 0) * L;
   float2 a[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + j + q * TPT) : make_float2(0.f, 0.f);
+  for (int q = 0; q < E; ++q) a[q] = ok ? ldh<kNtRowsFwd>(src, j + q * TPT) : make_float2(0.f, 0.f);
   float2 twr[reg_tw_count_mix<L>()];
   load_twiddles_reg_mix<L>(twr, j, tw);
   fft_reg<L, false, kTwMix>(a, j, x, twr);
@@ -102,7 +104,7 @@ __device__ __forceinline__ void rg_rows_fwd_pair(const float* __restrict__ in, f
     float2 a[E];
 #pragma unroll
     for (int q = 0; q < E; ++q)
-      a[q] = make_float2(ok ? __ldg(src + j + q * TPT) : 0.f, ok2 ? __ldg(src + L + j + q * TPT) : 0.f);
+      a[q] = make_float2(ok ? ldh<kNtRowsFwd>(src, j + q * TPT) : 0.f, ok2 ? ldh<kNtRowsFwd>(src + L, j + q * TPT) : 0.f);
     float2 twr[reg_tw_count_mix<L>()];
     load_twiddles_reg_mix<L>(twr, j, tw);
     fft_reg<L, false, kTwMix>(a, j, x, twr);
@@ -154,7 +156,7 @@ __device__ __forceinline__ void rg_cols(float2* __restrict__ ws, const RaggedIma
   const int64_t qs = (int64_t)(TPT / rb) * im.bs;
   float2 a[E];
 #pragma unroll
-  for (int q = 0; q < E; ++q) a[q] = ok ? base[q * qs] : make_float2(0.f, 0.f);
+  for (int q = 0; q < E; ++q) a[q] = ok ? ldh<kNtCols>(base + q * qs, 0) : make_float2(0.f, 0.f);
   float2 twr[reg_tw_count_mix<L>()];
   load_twiddles_reg_mix<L>(twr, ln.j, tw);
   fft_reg<L, false, kTwMix>(a, ln.j, x, twr);
@@ -198,7 +200,7 @@ __device__ __forceinline__ void rg_rows_inv(const float2* __restrict__ ws, void*
 #pragma unroll
       for (int i = 0; i < E / 2; ++i) {
         const int v = v0 + i * 2 * TPT;
-        const float4 y = __ldg(src + v * (rb >> 1));
+        const float4 y = ldh<kNtRowsInv>(src, v * (rb >> 1));
         x0[lds_pad(v)] = make_float2(y.x, y.y);
         x1[lds_pad(v)] = make_float2(y.z, y.w);
       }
@@ -208,7 +210,7 @@ __device__ __forceinline__ void rg_rows_inv(const float2* __restrict__ ws, void*
   } else {
     const float2* src = ws + im.ws_off + (int64_t)((ok ? u : 0) / rb) * im.bs + ((ok ? u : 0) % rb);
 #pragma unroll
-    for (int q = 0; q < E; ++q) a[q] = ok ? __ldg(src + (j + q * TPT) * rb) : make_float2(0.f, 0.f);
+    for (int q = 0; q < E; ++q) a[q] = ok ? ldh<kNtRowsInv>(src, (j + q * TPT) * rb) : make_float2(0.f, 0.f);
   }
   float2 twr[reg_tw_count_mix<L>()];
   load_twiddles_reg_mix<L>(twr, j, tw);

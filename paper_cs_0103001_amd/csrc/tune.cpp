@@ -44,9 +44,17 @@ int64_t filter_chunk(int64_t N, int64_t M, int64_t batch) {
 }
 
 int grad_groups(int64_t col_tiles, int64_t batch) {
-  constexpr int64_t kTarget = 2048;  // work items: several per resident workgroup slot
+  // work items (column tile, run of images): about two per CU, each over a
+  // long run.  Fewer, longer runs keep fewer images in flight at a time:
+  // batch 64 of 1024^2 took 304 / 258 / 246 / 293 us with runs of 8 / 16 /
+  // 32 / 64 images (non-temporal loads then took 32-image runs to 194 us).
+  int64_t target = 512;
+  if (const char* env = std::getenv("FFTMI_GRAD_TARGET")) {
+    const long long v = std::atoll(env);
+    if (v >= 1 && v <= (1 << 20)) target = v;
+  }
   if (batch <= 1 || col_tiles <= 0) return 1;
-  int64_t g = std::max<int64_t>(1, std::min<int64_t>(batch, kTarget / col_tiles));
+  int64_t g = std::max<int64_t>(1, std::min<int64_t>(batch, target / col_tiles));
   const int64_t per = (batch + g - 1) / g;
   return (int)((batch + per - 1) / per);
 }
