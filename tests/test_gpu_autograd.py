@@ -280,3 +280,51 @@ def test_learnable_wrappers_reject_short_spectrum():
         api.mask_grad(torch.zeros((2, 64, 64), dtype=torch.complex64, device="cuda"), spec[:16])
     with pytest.raises(ValueError):
         api.filter_mse(x, c, m.cpu(), 1.0)
+
+
+def test_gradient_run_lengths():
+    """The mask gradient with the batch split into runs of 1, 2, 4 and 16 images
+    (FFTMI_GRAD_TARGET at plan creation): each against the FP64 oracle, and the
+    different summation orders within float32 rounding of each other."""
+    import os
+    import torch
+    from paper_cs_0103001_amd import _binding as Bn
+    from paper_cs_0103001_amd import api
+    B, N, M = 16, 256, 256
+    noisy, clean = _pairs(B, N, M)
+    mask = np.random.default_rng(256).uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    _, L_ref, g_ref = oracle.loss_grad(noisy, clean, mask)
+    x, c, m = to_dev(noisy), to_dev(clean), to_dev(mask)
+    K = B * N * M
+    dev = x.device
+    st = api._stream(dev)
+    grads, runs_seen = [], set()
+    for target in (16, 32, 64, 256):
+        saved = os.environ.get("FFTMI_GRAD_TARGET")
+        os.environ["FFTMI_GRAD_TARGET"] = str(target)
+        try:
+            plan = api.Plan(2, (N, M), B, Bn.FFT_IN_REAL_F32, dev)
+        finally:
+            if saved is None:
+                os.environ.pop("FFTMI_GRAD_TARGET", None)
+            else:
+                os.environ["FFTMI_GRAD_TARGET"] = saved
+        runs = Bn.fft_plan_layout(plan.h)["grad_runs"]
+        runs_seen.add(runs)
+        announce("mse grad 16 x 256^2, target %d (%d runs)" % (target, runs))
+        ws = plan.workspace()
+        spec = torch.empty(plan.spectrum_bytes, dtype=torch.uint8, device=dev)
+        loss = torch.zeros((), dtype=torch.float32, device=dev)
+        grad = torch.empty((N, M), dtype=torch.float32, device=dev)
+        Bn.fft2d_filter_mse(plan.h, api._ptr(x), api._ptr(c), api._ptr(m), 1.0 / K, api._ptr(spec), api._ptr(loss),
+                            api._ptr(ws), st)
+        Bn.fft2d_filter_mse_grad(plan.h, api._ptr(x), api._ptr(c), api._ptr(spec), api._ptr(m), 2.0 / K,
+                                 api._ptr(grad), api._ptr(ws), st)
+        assert abs(float(loss) - L_ref) / L_ref < 1e-5, target
+        g = to_host(grad)
+        assert rel_l2(g, g_ref, 2) < TOL, (target, runs)
+        grads.append(g)
+    assert len(runs_seen) >= 3, runs_seen
+    for g in grads[1:]:
+        assert rel_l2(g, grads[0], 2) < 1e-6
+    del torch

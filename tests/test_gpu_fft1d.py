@@ -95,7 +95,7 @@ def test_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
-_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2", "FFTMI_FS_LOG_N1")
+_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2", "FFTMI_FS_LOG_N1", "FFTMI_FS_NT")
 
 
 def _fft_with(env, x, direction):
@@ -168,6 +168,24 @@ def test_fourstep_wide_tiles(lg):
             outs.append(got)
         for o in outs[1:]:
             assert rel_l2(o, outs[0], 1) < 1e-6
+
+
+@pytest.mark.parametrize("lg", [16, 20, 21])
+def test_fourstep_nontemporal_pass_two(lg):
+    """Pass two with and without the non-temporal loads and stores (on by
+    default up to 2^20 points): cache hints only, so both are bit-identical
+    and match the oracle in both directions."""
+    from paper_cs_0103001_amd import _binding as B
+    x = synth.uniform_complex((2, 1 << lg), (16, lg))
+    xd = to_dev(x)
+    for direction, ref in ((B.FFT_FORWARD, oracle.fft(x, threads=8)), (B.FFT_INVERSE, oracle.ifft(x, threads=8))):
+        outs = []
+        for nt in (0, 1):
+            announce("fft1d four-step n=2^%d dir %d non-temporal pass two %d" % (lg, direction, nt))
+            got, _ = _fft_with(dict(FFTMI_FS_NT=nt), xd, direction)
+            assert rel_l2(got, ref, 1) < TOL, nt
+            outs.append(got)
+        assert np.array_equal(outs[0], outs[1])
 
 
 @pytest.mark.parametrize("lg", [15, 20, 22])
