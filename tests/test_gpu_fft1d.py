@@ -95,7 +95,8 @@ def test_deterministic():
     np.testing.assert_array_equal(a, b)
 
 
-_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2", "FFTMI_FS_LOG_N1", "FFTMI_FS_NT")
+_FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2", "FFTMI_FS_LOG_N1", "FFTMI_FS_NT",
+             "FFTMI_FS_CHUNK_MB")
 
 
 def _fft_with(env, x, direction):
@@ -186,6 +187,27 @@ def test_fourstep_nontemporal_pass_two(lg):
             assert rel_l2(got, ref, 1) < TOL, nt
             outs.append(got)
         assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("lg", [16, 19])
+def test_fourstep_chunks(lg):
+    """The batch in chunks of batch entries (each chunk's two passes reuse the
+    start of the workspace), including a last chunk shorter than the others:
+    bit-identical to the whole batch at once, and the oracle's result."""
+    from paper_cs_0103001_amd import _binding as B
+    batch = 5
+    x = synth.uniform_complex((batch, 1 << lg), (17, lg))
+    xd = to_dev(x)
+    ref = oracle.fft(x, threads=8)
+    per_entry_mib = (1 << lg) * 8 / float(1 << 20)
+    outs = []
+    for mib in (0, int(2 * per_entry_mib) + 1, 128):  # whole batch, chunks of 2-3 entries, default
+        announce("fft1d four-step n=2^%d batch %d chunk %d MiB" % (lg, batch, mib))
+        got, _ = _fft_with(dict(FFTMI_FS_CHUNK_MB=mib), xd, B.FFT_FORWARD)
+        assert rel_l2(got, ref, 1) < TOL, mib
+        outs.append(got)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
 
 
 @pytest.mark.parametrize("lg", [15, 20, 22])
