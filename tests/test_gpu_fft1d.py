@@ -198,16 +198,16 @@ def test_fourstep_chunks(lg):
     batch = 5
     x = synth.uniform_complex((batch, 1 << lg), (17, lg))
     xd = to_dev(x)
-    ref = oracle.fft(x, threads=8)
     per_entry_mib = (1 << lg) * 8 / float(1 << 20)
-    outs = []
-    for mib in (0, int(2 * per_entry_mib) + 1, 128):  # whole batch, chunks of 2-3 entries, default
-        announce("fft1d four-step n=2^%d batch %d chunk %d MiB" % (lg, batch, mib))
-        got, _ = _fft_with(dict(FFTMI_FS_CHUNK_MB=mib), xd, B.FFT_FORWARD)
-        assert rel_l2(got, ref, 1) < TOL, mib
-        outs.append(got)
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
+    for direction, ref in ((B.FFT_FORWARD, oracle.fft(x, threads=8)), (B.FFT_INVERSE, oracle.ifft(x, threads=8))):
+        outs = []
+        for mib in (0, int(2 * per_entry_mib) + 1, 128):  # whole batch, chunks of 2-3 entries, default
+            announce("fft1d four-step n=2^%d batch %d chunk %d MiB dir %d" % (lg, batch, mib, direction))
+            got, _ = _fft_with(dict(FFTMI_FS_CHUNK_MB=mib), xd, direction)
+            assert rel_l2(got, ref, 1) < TOL, (mib, direction)
+            outs.append(got)
+        for o in outs[1:]:
+            assert np.array_equal(o, outs[0])
 
 
 @pytest.mark.parametrize("lg", [15, 20, 22])
