@@ -282,15 +282,17 @@ def test_learnable_wrappers_reject_short_spectrum():
         api.filter_mse(x, c, m.cpu(), 1.0)
 
 
-def test_gradient_run_lengths():
-    """The mask gradient with the batch split into runs of 1, 2, 4 and 16 images
-    (FFTMI_GRAD_TARGET at plan creation): each against the FP64 oracle, and the
-    different summation orders within float32 rounding of each other."""
+@pytest.mark.parametrize("B", [16, 13])
+def test_gradient_run_lengths(B):
+    """The mask gradient with the batch split into 1, 2, 4 and B runs of images
+    (FFTMI_GRAD_TARGET at plan creation; with 13 images the last run is
+    shorter): each against the FP64 oracle, and the different summation
+    orders within float32 rounding of each other."""
     import os
     import torch
     from paper_cs_0103001_amd import _binding as Bn
     from paper_cs_0103001_amd import api
-    B, N, M = 16, 256, 256
+    N, M = 256, 256
     noisy, clean = _pairs(B, N, M)
     mask = np.random.default_rng(256).uniform(0.2, 1.2, (N, M)).astype(np.float32)
     _, L_ref, g_ref = oracle.loss_grad(noisy, clean, mask)
@@ -311,7 +313,7 @@ def test_gradient_run_lengths():
                 os.environ["FFTMI_GRAD_TARGET"] = saved
         runs = Bn.fft_plan_layout(plan.h)["grad_runs"]
         runs_seen.add(runs)
-        announce("mse grad 16 x 256^2, target %d (%d runs)" % (target, runs))
+        announce("mse grad %d x 256^2, target %d (%d runs)" % (B, target, runs))
         ws = plan.workspace()
         spec = torch.empty(plan.spectrum_bytes, dtype=torch.uint8, device=dev)
         loss = torch.zeros((), dtype=torch.float32, device=dev)
