@@ -218,6 +218,39 @@ int fft2d_filter_mse(fft_plan_t plan, const float* x, const float* c, const floa
 int fft2d_filter_mse_grad(fft_plan_t plan, const void* x, const void* c, const void* spectrum, const float* mask,
                           float weight, float* grad_mask, void* workspace, void* stream);
 
+/* The same loss evaluated in the frequency domain, with a forward that also
+ * prepares its mask gradient.  The pair of eq. 5 and the 2D-IDFT inverts, so
+ * with the unnormalised spectra X = DFT2(x) and R = DFT2(x - c)
+ *   y - c = IDFT2((m - 1) X + R) / (N M)   and, by Parseval's relation,
+ *   loss[0] = weight * sum_b sum_{u,v} |(m - 1) X_b + R_b|^2 / (N M).
+ * No inverse transform is taken and y is never formed.  One complex
+ * transform per row of z = x + i (x - c) gives the row spectra of x and of
+ * x - c (split by the Hermitian symmetry of real rows); the column pass
+ * transforms both, adds the loss terms, and stores per run of images the
+ * per-bin sums of |X|^2 and Re(conj X . R) in `state`.
+ *   x, c    float32 [B][N][M] (device), mask m float32 [N][M] (device)
+ *   weight  e.g. 1 / (B N M) for the mean over all pixels
+ *   state   fft_spectrum_size(plan) bytes (device, 16-byte aligned): the row
+ *           spectra of x - c, then the sums the gradient reads; keep it
+ *           unchanged until fft2d_filter_mse_spectral_grad
+ *   loss    one float32 on the device
+ * The workspace receives the row spectra of x.  The loss terms are summed in
+ * float32 per thread over a run of images and in float64 across tiles, the
+ * per-bin sums over each run of images in order (deterministic).  Errors as
+ * fft2d_filter_mse; FFT_ERR_UNSUPPORTED also when rows per block times
+ * threads per row transform exceeds 1024 (M > 4096 at four rows per block). */
+int fft2d_filter_mse_spectral(fft_plan_t plan, const float* x, const float* c, const float* mask, float weight,
+                              void* state, float* loss, void* workspace, void* stream);
+
+/* Mask gradient of (weight/2) sum_b sum |y_b - c_b|^2 from the state of
+ * fft2d_filter_mse_spectral with the same plan (any mask m, since the sums
+ * do not depend on it):
+ *   grad_mask = weight * ((m - 1) sum_b |X_b|^2 + sum_b Re(conj X_b . R_b)) / (N M)
+ * with the runs added in order.  No transform is taken.  grad_mask float32
+ * [N][M] (device, overwritten).  Errors as fft2d_filter_mse_spectral. */
+int fft2d_filter_mse_spectral_grad(fft_plan_t plan, const void* state, const float* mask, float weight,
+                                   float* grad_mask, void* stream);
+
 /* Ragged batch: `count` square images of power-of-two sides sizes[i] (host
  * array, copied; 1 <= sizes[i] <= 2048), packed back to back in one buffer:
  * image i starts at element sum_{j<i} sizes[j]^2 and is row-major.  The plan

@@ -70,6 +70,8 @@ _SIGS = {
     "fft2d_filter_mask_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "fft2d_filter_mse_grad": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P]),
     "fft2d_filter_mse": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
+    "fft2d_filter_mse_spectral": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P]),
+    "fft2d_filter_mse_spectral_grad": (ctypes.c_int, [_P, _P, _P, ctypes.c_float, _P, _P]),
     "fft_plan_ragged": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int64, _I64P, ctypes.c_uint32]),
     "fft2d_filter_ragged": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
     "fft_plan_tune": (ctypes.c_int, [_P, _P, _P, _MASKP, _P, _P]),
@@ -196,6 +198,16 @@ def fft2d_filter_mse_grad(plan, x, c, spectrum, mask, weight, grad_mask, workspa
 def fft2d_filter_mse(plan, x, c, mask, weight, spectrum, loss, workspace, stream):
     check(lib().fft2d_filter_mse(plan, x, c, mask, float(weight), spectrum, loss, workspace, stream),
           "fft2d_filter_mse")
+
+
+def fft2d_filter_mse_spectral(plan, x, c, mask, weight, state, loss, workspace, stream):
+    check(lib().fft2d_filter_mse_spectral(plan, x, c, mask, float(weight), state, loss, workspace, stream),
+          "fft2d_filter_mse_spectral")
+
+
+def fft2d_filter_mse_spectral_grad(plan, state, mask, weight, grad_mask, stream):
+    check(lib().fft2d_filter_mse_spectral_grad(plan, state, mask, float(weight), grad_mask, stream),
+          "fft2d_filter_mse_spectral_grad")
 
 
 def fft2d_filter_ragged(plan, inp, out, mask, workspace, stream):

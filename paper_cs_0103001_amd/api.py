@@ -293,6 +293,49 @@ def filter_mse(x, c, mask, weight, norm="paper"):
     return loss, spec
 
 
+def filter_mse_spectral(x, c, mask, weight, norm="paper"):
+    """(loss, state): loss = weight * sum |2D-IDFT(m . 2D-DFT(x)) - c|^2 evaluated
+    in the frequency domain (no inverse transform), and the state that
+    mse_spectral_grad reads.  Raises FFTError(FFT_ERR_UNSUPPORTED) for shapes
+    the frequency-domain pass does not take (rows of more than 4096 points)."""
+    _check_images(x)
+    if not isinstance(c, torch.Tensor) or tuple(c.shape) != tuple(x.shape):
+        raise ValueError("c must have the shape of x %s" % (tuple(x.shape),))
+    if x.dtype != torch.float32 or c.dtype != torch.float32:
+        raise TypeError("filter_mse_spectral takes float32 images")
+    _check_mask_tensor(mask, x.shape[-2], x.shape[-1], x.device)
+    if c.device != x.device:
+        raise ValueError("c is on %s, x on %s" % (c.device, x.device))
+    x, fin = _prep(x)
+    c, _ = _prep(c)
+    N, M = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (N * M)
+    m = mask.contiguous()
+    plan = get_plan(2, (N, M), batch, fin | _NORM[norm], x.device)
+    state = torch.empty(max(plan.spectrum_bytes, 1), dtype=torch.uint8, device=x.device)
+    loss = torch.empty((), dtype=torch.float32, device=x.device)
+    ws = plan.workspace()
+    B.fft2d_filter_mse_spectral(plan.h, _ptr(x), _ptr(c), _ptr(m), weight, _ptr(state), _ptr(loss), _ptr(ws),
+                                _stream(x.device))
+    return loss, state
+
+
+def mse_spectral_grad(x, state, mask, weight, norm="paper"):
+    """weight * ((m - 1) sum_b |X_b|^2 + sum_b Re(conj X_b . R_b)) / (N M): the mask
+    gradient of (weight/2) sum |y - c|^2 from filter_mse_spectral's state for
+    the batch x (used for its shape and device only)."""
+    _check_images(x)
+    _check_mask_tensor(mask, x.shape[-2], x.shape[-1], x.device)
+    N, M = x.shape[-2], x.shape[-1]
+    batch = x.numel() // (N * M)
+    plan = get_plan(2, (N, M), batch, B.FFT_IN_REAL_F32 | _NORM[norm], x.device)
+    _check_spectrum(state, plan, x.device)
+    out = torch.empty((N, M), dtype=torch.float32, device=x.device)
+    B.fft2d_filter_mse_spectral_grad(plan.h, _ptr(state), _ptr(mask.contiguous()), weight, _ptr(out),
+                                     _stream(x.device))
+    return out
+
+
 def filter_ragged(packed, sizes, mask, real_output=False):
     """Ragged batch: square images of sizes[i]^2 packed back to back in one
     1D tensor (float32 or complex64); returns the filtered images, packed."""

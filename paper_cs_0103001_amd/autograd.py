@@ -51,8 +51,13 @@ class FFTFilterMSEFn(torch.autograd.Function):
     Evaluated through the exact identity y - c = 2D-IDFT((m - 1) . X) + (x - c),
     so that neither the loss nor its mask gradient subtracts nearly equal
     float32 values where the filter is close to the identity (m near 1, the
-    learnable mask's starting point).  Backward:
-      dL/dm = (2/K) sum_b [Re(conj X_b . 2D-IDFT^H(x_b - c_b)) + (N/M)(m - 1)|X_b|^2]
+    learnable mask's starting point).  The loss is taken in the frequency
+    domain (Parseval's relation: sum |y - c|^2 = sum |(m - 1) X + R|^2 / (N M)
+    for the unnormalised spectra X of x and R of x - c), and the forward also
+    forms the per-bin sums the mask gradient needs, so the backward takes no
+    transform; rows longer than 4096 points use the spatial-domain form.
+    Backward:
+      dL/dm = (2/K) sum_b [Re(conj X_b . R_b) + (m - 1)|X_b|^2] / (N M)
       dL/dx = (2/K) Re(filter_m(y - c)),   dL/dc = -(2/K)(y - c),
     with K = B N M and filter_m self-adjoint for a real mask.
     """
@@ -65,18 +70,28 @@ class FFTFilterMSEFn(torch.autograd.Function):
         x = x.contiguous()
         clean = clean.contiguous()
         K = clean.numel()
-        loss, spec = api.filter_mse(x, clean, m, 1.0 / K)
-        ctx.save_for_backward(spec, x, clean, m)
+        try:
+            loss, state = api.filter_mse_spectral(x, clean, m, 1.0 / K)
+            ctx.spectral = True
+        except api.B.FFTError as e:
+            if e.code != api.B.FFT_ERR_UNSUPPORTED:
+                raise
+            loss, state = api.filter_mse(x, clean, m, 1.0 / K)
+            ctx.spectral = False
+        ctx.save_for_backward(state, x, clean, m)
         ctx.K = K
         return loss
 
     @staticmethod
     def backward(ctx, gL):
-        spec, x, clean, m = ctx.saved_tensors
+        state, x, clean, m = ctx.saved_tensors
         K = ctx.K
         gx = gc = gm = None
         if ctx.needs_input_grad[2]:
-            gm = api.mse_grad(x, clean, spec, m, 2.0 / K) * gL
+            if ctx.spectral:
+                gm = api.mse_spectral_grad(x, state, m, 2.0 / K) * gL
+            else:
+                gm = api.mse_grad(x, clean, state, m, 2.0 / K) * gL
         if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
             r = api.fft2d_filter(x, m) - clean  # y - c (only for the image gradients)
             if ctx.needs_input_grad[0]:

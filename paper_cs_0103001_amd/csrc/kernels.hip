@@ -848,6 +848,176 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
   }
 }
 
+// ------------------------------------------------ MSE in the frequency domain
+// The filtered MSE and its mask gradient from the two spectra X = DFT2(x) and
+// R = DFT2(x - c), unnormalised.  The transform pair inverts, so
+//   y - c = IDFT2((m - 1) X + R) / (N M),
+// and Parseval's relation for the unnormalised DFT turns the spatial sum into
+//   sum |y - c|^2 = sum_{u,v} |(m - 1) X + R|^2 / (N M)
+// with mask gradient (2 / (N M)) [(m - 1) |X|^2 + Re(conj X . R)] per bin.
+// Pass 1 (k_rows_xd): one complex transform per row of z = x + i (x - c),
+// split by Hermitian symmetry into the row spectra of x and of x - c, both
+// stored in the blocked layout.  Pass 2 (k_cols_mse): the column transforms
+// of both, the loss terms, and per run of images the sums of |X|^2 and
+// Re(conj X . R) per bin.
+
+// A tile is one block of rows (rb rows, rb * TPT threads).
+template <int L>
+__global__ __launch_bounds__(1024) void k_rows_xd(const float* __restrict__ xin, const float* __restrict__ cin,
+                                                  float2* __restrict__ wsx, float2* __restrict__ wsd, int rb,
+                                                  unsigned bs, int ntiles, const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  constexpr int E = S::E, TPT = S::TPT, RBY = lds_region_bytes(L, 1);
+  static_assert(!kSplitExchange, "whole complex LDS entries");
+  char* reg = regions<L>();
+  const int tid = threadIdx.x, p = tid / TPT, j = tid - p * TPT;
+  const int nthr = rb * TPT;
+  const Twiddles<L> twd(tws, j);
+  const float2* tw = twd.ptr();
+  char* x = reg + p * RBY;
+  for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);  // block index over the batch
+    float2 a[E];
+    {
+      const int64_t row = (int64_t)t * rb + p;
+      const float* xb = xin + row * L;
+      const float* cb = cin + row * L;
+      const unsigned f = fresh((unsigned)j);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const float xv = ld_nt(xb, f + q * TPT);
+        a[q] = make_float2(xv, xv - ld_nt(cb, f + q * TPT));
+      }
+    }
+    fft_reg<L, false, S::TWM>(a, j, x, tw);
+    lds_barrier();  // the transform's last LDS reads are done
+    scatter_natural<L, kBoth>(a, j, x);
+    lds_barrier();
+    // column v of the block: rows 0 .. rb-1 of both spectra, two rows per float4
+    float4* ox = reinterpret_cast<float4*>(wsx + (int64_t)t * bs);
+    float4* od = reinterpret_cast<float4*>(wsd + (int64_t)t * bs);
+    const int v0 = (int)fresh((unsigned)tid);
+    for (int v = v0; v < L; v += nthr) {
+      const int vm = (L - v) & (L - 1);
+      for (int s = 0; s < rb; s += 2) {
+        const float2 z0 = reinterpret_cast<const float2*>(reg + s * RBY)[lds_pad(v)];
+        const float2 m0 = reinterpret_cast<const float2*>(reg + s * RBY)[lds_pad(vm)];
+        const float2 z1 = reinterpret_cast<const float2*>(reg + (s + 1) * RBY)[lds_pad(v)];
+        const float2 m1 = reinterpret_cast<const float2*>(reg + (s + 1) * RBY)[lds_pad(vm)];
+        // X = (Z + conj Z(-v)) / 2, D = (Z - conj Z(-v)) / 2i
+        ox[(v * rb + s) >> 1] = make_float4(0.5f * (z0.x + m0.x), 0.5f * (z0.y - m0.y), 0.5f * (z1.x + m1.x),
+                                            0.5f * (z1.y - m1.y));
+        od[(v * rb + s) >> 1] = make_float4(0.5f * (z0.y + m0.y), 0.5f * (m0.x - z0.x), 0.5f * (z1.y + m1.y),
+                                            0.5f * (m1.x - z1.x));
+      }
+    }
+    lds_barrier();  // the regions are read before the next tile's transform reuses them
+  }
+}
+
+// A tile is (run g of images, column tile): both column transforms per image,
+// the loss terms |(m - 1) X + R|^2 summed per thread, and per bin the run's
+// sums of |X|^2 and Re(conj X . R), stored to sumx[g] and sumxr[g]
+// (row-major [N][M]); the tile's loss sum goes to part[tile].
+template <int L>
+__global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restrict__ wsx,
+                                                           const float2* __restrict__ wsd,
+                                                           const float* __restrict__ mask, float* __restrict__ sumx,
+                                                           float* __restrict__ sumxr, float* __restrict__ part,
+                                                           int nimg, int per_group, int M, int rb, unsigned bs, int w,
+                                                           int ltiles, int ntiles, const float2* __restrict__ tws) {
+  using S = Shape<L>;
+  using C = GradCfg<L>;
+  constexpr int E = S::E, TPT = S::TPT;
+  const ColLanes ln = col_lanes(threadIdx.x, rb, w);
+  const Twiddles<L, C::TWM> twd(tws, ln.j);
+  const float2* tw = twd.ptr();
+  char* x = regions<L, C>() + ln.c * C::region(w);
+  const unsigned qs = (unsigned)(TPT / rb) * bs;
+  const unsigned qs_out = (unsigned)(TPT * M);
+  const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
+  const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
+  const int64_t plane = (int64_t)(L / rb) * bs;
+  const int tmask = (1 << ltiles) - 1;
+  float* red = reinterpret_cast<float*>(regions<L, C>());
+  for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
+    const int t = (int)tile_of(n, ntiles);
+    const int g = t >> ltiles, ct = t & tmask;
+    const int b0 = g * per_group, b1 = min(nimg, b0 + per_group);
+    float mv[E], ax[E], axr[E];
+    {
+      const float* mcol = mask + ct * w;
+      const unsigned f = fresh(lane_out);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        mv[q] = ld(mcol, f + q * qs_out) - 1.0f;
+        ax[q] = axr[q] = 0.f;
+      }
+    }
+    float lacc = 0.f;
+    for (int bi = b0; bi < b1; ++bi) {
+      float2 X[E], R[E];
+      {
+        const float2* b = wsx + bi * plane + ct * w * rb;
+        const unsigned f = fresh(lane);
+#pragma unroll
+        for (int q = 0; q < E; ++q) X[q] = ld_nt(b, f + q * qs);
+      }
+      fft_reg<L, false, C::TWM, C::SPLIT>(X, ln.j, x, tw);
+      {
+        const float2* b = wsd + bi * plane + ct * w * rb;
+        const unsigned f = fresh(lane);
+#pragma unroll
+        for (int q = 0; q < E; ++q) R[q] = ld_nt(b, f + q * qs);
+      }
+      fft_reg<L, false, C::TWM, C::SPLIT>(R, ln.j, x, tw);
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        ax[q] = fmaf(X[q].x, X[q].x, fmaf(X[q].y, X[q].y, ax[q]));
+        axr[q] = fmaf(X[q].x, R[q].x, fmaf(X[q].y, R[q].y, axr[q]));
+        const float ex = fmaf(mv[q], X[q].x, R[q].x), ey = fmaf(mv[q], X[q].y, R[q].y);
+        lacc = fmaf(ex, ex, fmaf(ey, ey, lacc));
+      }
+    }
+    {
+      const unsigned f = fresh(lane_out);
+      float* dx = sumx + (int64_t)g * L * M + ct * w;
+      float* dxr = sumxr + (int64_t)g * L * M + ct * w;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        dx[f + q * qs_out] = ax[q];
+        dxr[f + q * qs_out] = axr[q];
+      }
+    }
+    // the tile's loss sum: an LDS tree over the workgroup, in a fixed order
+    const int tid = threadIdx.x;
+    lds_barrier();  // the last transform's LDS reads are done
+    red[tid] = lacc;
+    lds_barrier();
+    for (int h = (int)blockDim.x >> 1; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      lds_barrier();
+    }
+    if (tid == 0) part[t] = red[0];
+    lds_barrier();  // red read before the next tile's transform reuses LDS
+  }
+}
+
+// grad[i] = w * ((m_i - 1) * sum_g sumx[g][i] + sum_g sumxr[g][i]), the runs
+// added in order.
+__global__ __launch_bounds__(256) void k_mse_grad_sums(const float* __restrict__ sumx, const float* __restrict__ sumxr,
+                                                       const float* __restrict__ mask, float* __restrict__ grad,
+                                                       int64_t n, int groups, float w) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    float sx = sumx[i], sxr = sumxr[i];
+    for (int g = 1; g < groups; ++g) {
+      sx += sumx[g * n + i];
+      sxr += sumxr[g * n + i];
+    }
+    grad[i] = w * fmaf(mask[i] - 1.0f, sx, sxr);
+  }
+}
+
 // grad[i] = part[0][i] + part[1][i] + ... + part[G-1][i], in that order.
 __global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ part, float4* __restrict__ grad,
                                                     int64_t n4, int groups) {
@@ -1290,6 +1460,41 @@ struct ColsGrad {
 };
 
 template <int LG>
+struct RowsXd {
+  static hipError_t run(const float* x, const float* c, float2* wsx, float2* wsd, int64_t blocks, int rb, unsigned bs,
+                        const Launch& lc) {
+    constexpr int L = 1 << LG, TPT = threads_per_transform(L);
+    if constexpr (L < 2) {
+      return hipErrorInvalidValue;
+    } else {
+      if (rb < 2 || rb % 2 || rb * TPT > 1024) return hipErrorInvalidValue;
+      const int lds = tw_bytes<L>() + rb * lds_region_bytes(L, 1);
+      if (lds > kLdsBytes) return hipErrorInvalidValue;
+      return go(k_rows_xd<L>, blocks, rb * TPT, lds, lc.stream, x, c, wsx, wsd, rb, bs, (int)blocks,
+                twiddle_src<L>(lc));
+    }
+  }
+};
+
+template <int LG>
+struct ColsMse {
+  static hipError_t run(const float2* wsx, const float2* wsd, const float* mask, float* sumx, float* sumxr,
+                        float* part, int64_t nimg, int groups, int M, int rb, unsigned bs, int w, int64_t* ntiles_out,
+                        const Launch& lc) {
+    constexpr int L = 1 << LG, TPT = threads_per_transform(L);
+    using C = GradCfg<L>;
+    const int lds = std::max(C::TWB + w * C::region(w), (int)(w * TPT * sizeof(float)));
+    const int ctiles = M / w;
+    const int per_group = (int)((nimg + groups - 1) / groups);
+    const int64_t ntiles = (int64_t)groups * ctiles;
+    *ntiles_out = ntiles;
+    const int lt = ilog2c(ctiles);
+    return go(k_cols_mse<L>, ntiles, w * TPT, lds, lc.stream, wsx, wsd, mask, sumx, sumxr, part, (int)nimg, per_group,
+              M, rb, bs, w, lt, (int)ntiles, twiddle_src<L, C>(lc));
+  }
+};
+
+template <int LG>
 struct ColsStrided {
   template <bool INV, bool WIDE, bool TT>
   static hipError_t go_one(const float2* in, float2* out, int64_t ntiles, int w, int lds, int C, int lt, float scale,
@@ -1362,6 +1567,12 @@ struct ColsStrided {
 #define FFTMI_CASE_ColsGrad(K) \
   case K:                      \
     return ColsGrad<K>::run(ws, save, mask, part, nimg, groups, M, rb, bs, w, w_lin, w_sq, lc);
+#define FFTMI_CASE_RowsXd(K) \
+  case K:                    \
+    return RowsXd<K>::run(x, c, wsx, wsd, blocks, rb, bs, lc);
+#define FFTMI_CASE_ColsMse(K) \
+  case K:                     \
+    return ColsMse<K>::run(wsx, wsd, mask, sumx, sumxr, part, nimg, groups, M, rb, bs, w, ntiles, lc);
 #define FFTMI_CASE_ColsStrided(K) \
   case K:                         \
     return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_fs, in_bstride, in_rstride, \
@@ -1520,6 +1731,26 @@ hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, con
                             int64_t nimg, int groups, int M, int rb, unsigned bs, int w, float w_lin, float w_sq,
                             const Launch& lc) {
   FFTMI_DISPATCH(ColsGrad, log2L)
+}
+
+hipError_t launch_rows_xd(int log2L, const float* x, const float* c, float2* wsx, float2* wsd, int64_t blocks, int rb,
+                          unsigned bs, const Launch& lc) {
+  FFTMI_DISPATCH(RowsXd, log2L)
+}
+
+hipError_t launch_cols_mse(int log2L, const float2* wsx, const float2* wsd, const float* mask, float* sumx,
+                           float* sumxr, float* part, int64_t nimg, int groups, int M, int rb, unsigned bs, int w,
+                           int64_t* ntiles, const Launch& lc) {
+  FFTMI_DISPATCH(ColsMse, log2L)
+}
+
+hipError_t launch_mse_grad_sums(const float* sumx, const float* sumxr, const float* mask, float* grad, int64_t n,
+                                int groups, float w, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_mse_grad_sums, dim3((unsigned)blocks), dim3(256), 0, stream, sumx, sumxr, mask, grad, n, groups,
+                     w);
+  return hipGetLastError();
 }
 
 hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int groups, hipStream_t stream) {

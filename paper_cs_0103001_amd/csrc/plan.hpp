@@ -72,6 +72,7 @@ struct fftmi_plan {
   // offsets of their partial sums and of the fused MSE forward's per-tile sums
   int grad_groups = 1;
   size_t part_off = 0, loss_off = 0, loss_mid_off = 0;
+  size_t mse_sums_off = 0;  // in the saved-state buffer of the frequency-domain MSE
   // rank 2 with columns of 2048 points or more (tiles of one or two columns):
   // workspace offset of a transposed copy of a tensor mask (0: none)
   size_t maskt_off = 0;

@@ -330,3 +330,63 @@ def test_gradient_run_lengths(B):
     for g in grads[1:]:
         assert rel_l2(g, grads[0], 2) < 1e-6
     del torch
+
+
+@pytest.mark.parametrize("B,N,M", [(3, 64, 64), (2, 32, 128), (2, 128, 32), (4, 256, 256), (16, 1024, 1024),
+                                   (1, 4096, 64), (1, 64, 4096), (2, 2048, 512)])
+def test_spectral_mse_vs_oracle_and_spatial_form(B, N, M):
+    """The frequency-domain MSE (fft2d_filter_mse_spectral and its gradient)
+    against the FP64 oracle's loss and gradient, and against the spatial-domain
+    fused pair (fft2d_filter_mse, fft2d_filter_mse_grad) on the same inputs."""
+    from paper_cs_0103001_amd import api
+    noisy, clean = _pairs(B, N, M)
+    mask = np.random.default_rng(N + M).uniform(0.2, 1.2, (N, M)).astype(np.float32)
+    x, c, m = to_dev(noisy), to_dev(clean), to_dev(mask)
+    K = B * N * M
+    announce("spectral mse %d x %dx%d" % (B, N, M))
+    loss, state = api.filter_mse_spectral(x, c, m, 1.0 / K)
+    g = to_host(api.mse_spectral_grad(x, state, m, 2.0 / K))
+    _, L_ref, g_ref = oracle.loss_grad(noisy, clean, mask)
+    lerr = abs(float(loss) - L_ref) / L_ref
+    gerr = rel_l2(g, g_ref, 2)
+    print("spectral mse %d x %dx%d: loss rel %.2e, grad relL2 %.2e" % (B, N, M, lerr, gerr))
+    assert lerr < 1e-5
+    assert gerr < TOL
+    loss2, spec = api.filter_mse(x, c, m, 1.0 / K)
+    g2 = to_host(api.mse_grad(x, c, spec, m, 2.0 / K))
+    assert abs(float(loss) - float(loss2)) / float(loss2) < 1e-5
+    assert rel_l2(g, g2, 2) < TOL
+
+
+def test_spectral_mse_at_mask_one_and_unsupported_rows():
+    """At m = 1 the loss is sum |R|^2 / (N M) exactly (no cancellation) and the
+    gradient is sum Re(conj X . R); rows of 8192 points are refused with
+    FFT_ERR_UNSUPPORTED and the autograd function then takes the spatial form.
+    (x and c here differ, so sum |R|^2 > 0.)"""
+    import torch
+    from paper_cs_0103001_amd import _binding as Bn
+    from paper_cs_0103001_amd import api
+    from paper_cs_0103001_amd.autograd import fft_filter_mse
+    B, N, M = 4, 512, 512
+    noisy, clean = _pairs(B, N, M)
+    mask = np.ones((N, M), np.float32)
+    x, c, m = to_dev(noisy), to_dev(clean), to_dev(mask)
+    K = B * N * M
+    loss, state = api.filter_mse_spectral(x, c, m, 1.0 / K)
+    g = to_host(api.mse_spectral_grad(x, state, m, 2.0 / K))
+    _, L_ref, g_ref = oracle.loss_grad(noisy, clean, mask)
+    assert abs(float(loss) - L_ref) / L_ref < 1e-6
+    assert rel_l2(g, g_ref, 2) < TOL
+    # 64 x 8192: four rows per block of 512-thread transforms exceed one workgroup
+    n2, c2 = _pairs(1, 64, 8192)
+    xd, cd = to_dev(n2), to_dev(c2)
+    m2 = torch.ones((64, 8192), dtype=torch.float32, device=xd.device)
+    with pytest.raises(Bn.FFTError) as ei:
+        api.filter_mse_spectral(xd, cd, m2, 1.0)
+    assert ei.value.code == Bn.FFT_ERR_UNSUPPORTED
+    mr = m2.clone().requires_grad_(True)
+    L = fft_filter_mse(xd, cd, mr)
+    L.backward()
+    _, L_ref2, g_ref2 = oracle.loss_grad(n2, c2, np.ones((64, 8192), np.float32))
+    assert abs(float(L) - L_ref2) / L_ref2 < 1e-5
+    assert rel_l2(to_host(mr.grad), g_ref2, 2) < TOL
