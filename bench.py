@@ -327,10 +327,10 @@ def main():
         ms_fb = timed(torch, fwd_bwd, Kl, 2, WARM_MS)
         pxl = Bl * Nl * Ml
         # library kernels (the loss in the frequency domain): rows of x and of
-        # x - c from x and c (4 + 4 read, 8 + 8 written), columns of both row
-        # spectra (8 + 8 read); the per-bin sums, the mask and the backward's
-        # sums are a few bytes per bin, not per pixel
-        fb_bytes = 40 * pxl
+        # x - c from x and c (4 + 4 read; columns 0 .. M/2 of both row
+        # spectra, 4 + 4 written), columns of both (4 + 4 read); the per-bin
+        # sums, the mask and the backward's sums are a few bytes per bin
+        fb_bytes = 24 * pxl
         planl = api.get_plan(2, (Nl, Ml), Bl, B.FFT_IN_REAL_F32, dev)
         wsl = planl.workspace()
         ol = torch.empty((Bl, Nl, Ml), dtype=torch.complex64, device=dev)
@@ -342,9 +342,9 @@ def main():
         result["fwd_bwd"] = {"workload": "learn_1024: batch 64 of 1024x1024, learnable float32 mask at 1, "
                                          "MSE loss (fused filter+MSE op, frequency-domain form), mask gradient",
                              "ms_per_step": round(ms_fb, 4), "GB/s": round(fb_gbs, 1),
-                             "byte_model": "40 B/px of library kernels (rows of x and x - c: 8 read + 16 written; "
-                                           "columns of both row spectra: 16 read; loss and per-bin sums in the "
-                                           "frequency domain, backward from the sums)",
+                             "byte_model": "24 B/px of library kernels (rows of x and x - c: 8 read + 8 written, "
+                                           "columns 0..M/2 of both row spectra; their columns: 8 read; loss and "
+                                           "per-bin sums in the frequency domain, backward from the sums)",
                              "plain_same_batch_ms": round(ms_pl, 4), "plain_same_batch_GB/s": round(plain_gbs, 1),
                              "time_vs_plain_same_batch": round(ms_fb / ms_pl, 3),
                              "ns_per_px": round(ms_fb * 1e6 / pxl, 4),

@@ -388,7 +388,14 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
     if (!p->half) {
       p->loss_off = (p->ws_bytes + 255) & ~(size_t)255;
       // (the frequency-domain MSE has one per (run, column tile))
-      const int64_t nparts = std::max<int64_t>({batch * N, (int64_t)p->grad_groups * (M / p->w), (int64_t)1});
+      // the frequency-domain MSE's layout: columns 0 .. M/2 of the row
+      // spectra, in column tiles of mse_w, padded to mse_mh columns
+      p->mse_w = (int)std::max<int64_t>(1, std::min<int64_t>(p->w, M / 2));
+      p->mse_mh = (int)((M / 2) / p->mse_w + 1) * p->mse_w;
+      p->mse_bs = rb * p->mse_mh + fftmi::block_pad(rb * p->mse_mh);
+      p->mse_img = (N / rb) * p->mse_bs;
+      const int64_t nparts =
+          std::max<int64_t>({batch * N, (int64_t)p->grad_groups * (p->mse_mh / p->mse_w), (int64_t)1});
       p->loss_mid_off = (p->loss_off + (size_t)nparts * sizeof(float) + 255) & ~(size_t)255;
       p->ws_bytes = p->loss_mid_off + (size_t)sum_partials_scratch(nparts) * sizeof(double);
       // columns of 2048 points or more go in tiles of one or two columns, so
@@ -398,10 +405,11 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
         p->maskt_off = (p->ws_bytes + 255) & ~(size_t)255;
         p->ws_bytes = p->maskt_off + maskt_bytes(p.get());
       }
-      // the frequency-domain MSE keeps, after the row spectra of x - c, the
-      // per-run sums of |X|^2 and Re(conj X . R) per bin for its gradient
-      p->mse_sums_off = (p->spec_bytes + 255) & ~(size_t)255;
-      p->spec_bytes = p->mse_sums_off + 2 * (size_t)p->grad_groups * (size_t)N * (size_t)M * sizeof(float);
+      // the frequency-domain MSE's state: the stored row spectra of x - c,
+      // then the per-run sums of |X|^2 and Re(conj X . R) per stored bin
+      p->mse_sums_off = ((size_t)batch * (size_t)p->mse_img * sizeof(float2) + 255) & ~(size_t)255;
+      p->spec_bytes = std::max(p->spec_bytes, p->mse_sums_off + 2 * (size_t)p->grad_groups * (size_t)N *
+                                                                    (size_t)p->mse_mh * sizeof(float));
     }
   }
   plan_register(p.get());
@@ -791,14 +799,20 @@ int fft2d_filter_mse(fft_plan_t p, const float* x, const float* c, const float* 
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 
+// Plans the frequency-domain MSE takes: real rank-2 input without padding
+// or half spectra, rows of at least 4 points, and rb rows of one block
+// transformed by one workgroup.
+static bool mse_spectral_ok(const fftmi_plan* p) {
+  return !p->padded && !p->half && (p->flags & FFT_IN_REAL_F32) && p->rb >= 2 && p->rb % 2 == 0 && p->m >= 4 &&
+         (int64_t)p->rb * threads_per_transform((int)p->m) <= 1024;
+}
+
 int fft2d_filter_mse_spectral(fft_plan_t p, const float* x, const float* c, const float* mask, float weight,
                               void* state, float* loss, void* workspace, void* stream) {
   TraceRange tr("fft2d_filter_mse_spectral");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
-  if (p->padded || p->half || !(p->flags & FFT_IN_REAL_F32) || p->rb < 2 || p->rb % 2 ||
-      (int64_t)p->rb * threads_per_transform((int)p->m) > 1024)
-    return FFT_ERR_UNSUPPORTED;
+  if (!mse_spectral_ok(p)) return FFT_ERR_UNSUPPORTED;
   if (!loss) return FFT_ERR_ARG;
   if (p->batch > 0 && (!x || !c || !mask || !state)) return FFT_ERR_ARG;
   if (!workspace) return FFT_ERR_WORKSPACE;
@@ -817,15 +831,15 @@ int fft2d_filter_mse_spectral(fft_plan_t p, const float* x, const float* c, cons
   float2* wsx = static_cast<float2*>(workspace);
   float2* wsd = static_cast<float2*>(state);
   float* sumx = reinterpret_cast<float*>(static_cast<char*>(state) + p->mse_sums_off);
-  float* sumxr = sumx + (size_t)p->grad_groups * (size_t)(p->n * p->m);
-  const unsigned bs = (unsigned)p->bs;
+  float* sumxr = sumx + (size_t)p->grad_groups * (size_t)p->n * (size_t)p->mse_mh;
+  const unsigned bs = (unsigned)p->mse_bs;
   Launch lr = launch_for(st, p->tables, p->log_m);
   Launch lcn = launch_for(st, p->tables, p->log_n);
   hipError_t e = launch_rows_xd(p->log_m, x, c, wsx, wsd, p->batch * p->n / p->rb, p->rb, bs, lr);
   if (e != hipSuccess) return hip_fail(e);
   int64_t nparts = 0;
-  e = launch_cols_mse(p->log_n, wsx, wsd, mask, sumx, sumxr, part, p->batch, p->grad_groups, (int)p->m, p->rb, bs,
-                      p->w, &nparts, lcn);
+  e = launch_cols_mse(p->log_n, wsx, wsd, mask, sumx, sumxr, part, p->batch, p->grad_groups, (int)p->m, p->mse_mh,
+                      p->rb, bs, p->mse_w, &nparts, lcn);
   if (e != hipSuccess) return hip_fail(e);
   e = launch_sum_partials(part, nparts, lw, loss, mid, st);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
@@ -836,9 +850,7 @@ int fft2d_filter_mse_spectral_grad(fft_plan_t p, const void* state, const float*
   TraceRange tr("fft2d_filter_mse_spectral_grad");
   if (!plan_live(p)) return FFT_ERR_ARG;
   if (p->kind != 2) return FFT_ERR_STATE;
-  if (p->padded || p->half || !(p->flags & FFT_IN_REAL_F32) || p->rb < 2 || p->rb % 2 ||
-      (int64_t)p->rb * threads_per_transform((int)p->m) > 1024)
-    return FFT_ERR_UNSUPPORTED;
+  if (!mse_spectral_ok(p)) return FFT_ERR_UNSUPPORTED;
   if (!grad_mask || !mask) return FFT_ERR_ARG;
   if (p->batch > 0 && !state) return FFT_ERR_ARG;
   int rc = check_plan(p, nullptr);
@@ -850,10 +862,11 @@ int fft2d_filter_mse_spectral_grad(fft_plan_t p, const void* state, const float*
     return e == hipSuccess ? FFT_OK : hip_fail(e);
   }
   const float* sumx = reinterpret_cast<const float*>(static_cast<const char*>(state) + p->mse_sums_off);
-  const float* sumxr = sumx + (size_t)p->grad_groups * (size_t)nm;
+  const float* sumxr = sumx + (size_t)p->grad_groups * (size_t)p->n * (size_t)p->mse_mh;
   // (weight / 2) d/dm sum |y - c|^2 = weight ((m - 1) sum |X|^2 + sum Re(conj X . R)) / (N M)
   const float gw = (float)((double)weight / ((double)p->n * (double)p->m));
-  hipError_t e = launch_mse_grad_sums(sumx, sumxr, mask, grad_mask, nm, p->grad_groups, gw, st);
+  hipError_t e = launch_mse_grad_sums(sumx, sumxr, mask, grad_mask, (int)p->n, (int)p->m, p->mse_mh, p->grad_groups,
+                                      gw, st);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }
 

@@ -855,13 +855,19 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_grad(const float2* __rest
 // and Parseval's relation for the unnormalised DFT turns the spatial sum into
 //   sum |y - c|^2 = sum_{u,v} |(m - 1) X + R|^2 / (N M)
 // with mask gradient (2 / (N M)) [(m - 1) |X|^2 + Re(conj X . R)] per bin.
+// x and c are real, so X(N-u, M-v) = conj X(u, v) and likewise R: columns
+// v = 0 .. M/2 of the spectra carry every bin, and a bin (u, v) with
+// 0 < v < M/2 stands for itself and for its mirror (N-u, M-v), which has the
+// same |X|^2, Re(conj X . R) and |.|^2 of a loss term (with its own mask
+// value).
 // Pass 1 (k_rows_xd): one complex transform per row of z = x + i (x - c),
-// split by Hermitian symmetry into the row spectra of x and of x - c, both
-// stored in the blocked layout.  Pass 2 (k_cols_mse): the column transforms
-// of both, the loss terms, and per run of images the sums of |X|^2 and
-// Re(conj X . R) per bin.
+// split by Hermitian symmetry into the row spectra of x and of x - c;
+// columns 0 .. M/2 of both are stored in a blocked layout of mh columns.
+// Pass 2 (k_cols_mse): the column transforms of both, the loss terms, and
+// per run of images the sums of |X|^2 and Re(conj X . R) per stored bin.
 
-// A tile is one block of rows (rb rows, rb * TPT threads).
+// A tile is one block of rows (rb rows, rb * TPT threads); bs is the block
+// stride of the mh-column layout.
 template <int L>
 __global__ __launch_bounds__(1024) void k_rows_xd(const float* __restrict__ xin, const float* __restrict__ cin,
                                                   float2* __restrict__ wsx, float2* __restrict__ wsd, int rb,
@@ -893,11 +899,12 @@ __global__ __launch_bounds__(1024) void k_rows_xd(const float* __restrict__ xin,
     lds_barrier();  // the transform's last LDS reads are done
     scatter_natural<L, kBoth>(a, j, x);
     lds_barrier();
-    // column v of the block: rows 0 .. rb-1 of both spectra, two rows per float4
+    // column v = 0 .. L/2 of the block: rows 0 .. rb-1 of both spectra, two
+    // rows per float4
     float4* ox = reinterpret_cast<float4*>(wsx + (int64_t)t * bs);
     float4* od = reinterpret_cast<float4*>(wsd + (int64_t)t * bs);
     const int v0 = (int)fresh((unsigned)tid);
-    for (int v = v0; v < L; v += nthr) {
+    for (int v = v0; v <= L / 2; v += nthr) {
       const int vm = (L - v) & (L - 1);
       for (int s = 0; s < rb; s += 2) {
         const float2 z0 = reinterpret_cast<const float2*>(reg + s * RBY)[lds_pad(v)];
@@ -915,17 +922,20 @@ __global__ __launch_bounds__(1024) void k_rows_xd(const float* __restrict__ xin,
   }
 }
 
-// A tile is (run g of images, column tile): both column transforms per image,
-// the loss terms |(m - 1) X + R|^2 summed per thread, and per bin the run's
-// sums of |X|^2 and Re(conj X . R), stored to sumx[g] and sumxr[g]
-// (row-major [N][M]); the tile's loss sum goes to part[tile].
+// A tile is (run g of images, column tile ct of `tiles` per run): both
+// column transforms per image for the stored columns v = ct*w + c <= M/2,
+// the loss terms of the bin and of its mirror summed per thread, and per bin
+// the run's sums of |X|^2 and Re(conj X . R), stored to sumx[g] and
+// sumxr[g] ([N][mh]); the tile's loss sum goes to part[tile].  Columns of
+// the last tile beyond M/2 are not read and add nothing.
 template <int L>
 __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restrict__ wsx,
                                                            const float2* __restrict__ wsd,
                                                            const float* __restrict__ mask, float* __restrict__ sumx,
                                                            float* __restrict__ sumxr, float* __restrict__ part,
-                                                           int nimg, int per_group, int M, int rb, unsigned bs, int w,
-                                                           int ltiles, int ntiles, const float2* __restrict__ tws) {
+                                                           int nimg, int per_group, int M, int mh, int rb, unsigned bs,
+                                                           int w, int tiles, int ntiles,
+                                                           const float2* __restrict__ tws) {
   using S = Shape<L>;
   using C = GradCfg<L>;
   constexpr int E = S::E, TPT = S::TPT;
@@ -934,23 +944,25 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
   const float2* tw = twd.ptr();
   char* x = regions<L, C>() + ln.c * C::region(w);
   const unsigned qs = (unsigned)(TPT / rb) * bs;
-  const unsigned qs_out = (unsigned)(TPT * M);
   const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
-  const unsigned lane_out = (unsigned)(ln.j * M + ln.c);
   const int64_t plane = (int64_t)(L / rb) * bs;
-  const int tmask = (1 << ltiles) - 1;
   float* red = reinterpret_cast<float*>(regions<L, C>());
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
-    const int g = t >> ltiles, ct = t & tmask;
+    const int g = t / tiles, ct = t - g * tiles;
     const int b0 = g * per_group, b1 = min(nimg, b0 + per_group);
-    float mv[E], ax[E], axr[E];
+    const int v = ct * w + ln.c;
+    const bool ok = v <= M / 2;                // a stored column
+    const bool mir = ok && v > 0 && v < M / 2;  // it also stands for column M - v
+    // mask values minus one at the bin (u, v) and at its mirror (N - u, M - v)
+    float m1[E], m2[E], ax[E], axr[E];
     {
-      const float* mcol = mask + ct * w;
-      const unsigned f = fresh(lane_out);
+      const int jf = (int)fresh((unsigned)ln.j);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        mv[q] = ld(mcol, f + q * qs_out) - 1.0f;
+        const int u = jf + q * TPT;
+        m1[q] = ok ? ld(mask, (unsigned)(u * M + v)) - 1.0f : 0.f;
+        m2[q] = mir ? ld(mask, (unsigned)(((L - u) & (L - 1)) * M + (M - v))) - 1.0f : 0.f;
         ax[q] = axr[q] = 0.f;
       }
     }
@@ -961,32 +973,35 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
         const float2* b = wsx + bi * plane + ct * w * rb;
         const unsigned f = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) X[q] = ld_nt(b, f + q * qs);
+        for (int q = 0; q < E; ++q) X[q] = ok ? ld_nt(b, f + q * qs) : make_float2(0.f, 0.f);
       }
       fft_reg<L, false, C::TWM, C::SPLIT>(X, ln.j, x, tw);
       {
         const float2* b = wsd + bi * plane + ct * w * rb;
         const unsigned f = fresh(lane);
 #pragma unroll
-        for (int q = 0; q < E; ++q) R[q] = ld_nt(b, f + q * qs);
+        for (int q = 0; q < E; ++q) R[q] = ok ? ld_nt(b, f + q * qs) : make_float2(0.f, 0.f);
       }
       fft_reg<L, false, C::TWM, C::SPLIT>(R, ln.j, x, tw);
 #pragma unroll
       for (int q = 0; q < E; ++q) {
         ax[q] = fmaf(X[q].x, X[q].x, fmaf(X[q].y, X[q].y, ax[q]));
         axr[q] = fmaf(X[q].x, R[q].x, fmaf(X[q].y, R[q].y, axr[q]));
-        const float ex = fmaf(mv[q], X[q].x, R[q].x), ey = fmaf(mv[q], X[q].y, R[q].y);
+        const float ex = fmaf(m1[q], X[q].x, R[q].x), ey = fmaf(m1[q], X[q].y, R[q].y);
+        const float fx = fmaf(m2[q], X[q].x, R[q].x), fy = fmaf(m2[q], X[q].y, R[q].y);
         lacc = fmaf(ex, ex, fmaf(ey, ey, lacc));
+        if (mir) lacc = fmaf(fx, fx, fmaf(fy, fy, lacc));
       }
     }
-    {
-      const unsigned f = fresh(lane_out);
-      float* dx = sumx + (int64_t)g * L * M + ct * w;
-      float* dxr = sumxr + (int64_t)g * L * M + ct * w;
+    if (ok) {
+      const unsigned f = (unsigned)(fresh((unsigned)ln.j) * mh + v);
+      const unsigned qo = (unsigned)(TPT * mh);
+      float* dx = sumx + (int64_t)g * L * mh;
+      float* dxr = sumxr + (int64_t)g * L * mh;
 #pragma unroll
       for (int q = 0; q < E; ++q) {
-        dx[f + q * qs_out] = ax[q];
-        dxr[f + q * qs_out] = axr[q];
+        dx[f + q * qo] = ax[q];
+        dxr[f + q * qo] = axr[q];
       }
     }
     // the tile's loss sum: an LDS tree over the workgroup, in a fixed order
@@ -1003,16 +1018,19 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
   }
 }
 
-// grad[i] = w * ((m_i - 1) * sum_g sumx[g][i] + sum_g sumxr[g][i]), the runs
-// added in order.
+// grad[u][v] = w * ((m - 1) * sum_g sumx[g] + sum_g sumxr[g]) at the stored
+// bin (u, v), or at (N - u, M - v) for v > M/2; the runs added in order.
 __global__ __launch_bounds__(256) void k_mse_grad_sums(const float* __restrict__ sumx, const float* __restrict__ sumxr,
-                                                       const float* __restrict__ mask, float* __restrict__ grad,
-                                                       int64_t n, int groups, float w) {
+                                                       const float* __restrict__ mask, float* __restrict__ grad, int N,
+                                                       int M, int mh, int groups, float w) {
+  const int64_t n = (int64_t)N * M, plane = (int64_t)N * mh;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    float sx = sumx[i], sxr = sumxr[i];
+    const int u = (int)(i / M), v = (int)(i - (int64_t)u * M);
+    const int64_t k = v <= M / 2 ? (int64_t)u * mh + v : (int64_t)((N - u) & (N - 1)) * mh + (M - v);
+    float sx = sumx[k], sxr = sumxr[k];
     for (int g = 1; g < groups; ++g) {
-      sx += sumx[g * n + i];
-      sxr += sumxr[g * n + i];
+      sx += sumx[g * plane + k];
+      sxr += sumxr[g * plane + k];
     }
     grad[i] = w * fmaf(mask[i] - 1.0f, sx, sxr);
   }
@@ -1479,18 +1497,18 @@ struct RowsXd {
 template <int LG>
 struct ColsMse {
   static hipError_t run(const float2* wsx, const float2* wsd, const float* mask, float* sumx, float* sumxr,
-                        float* part, int64_t nimg, int groups, int M, int rb, unsigned bs, int w, int64_t* ntiles_out,
-                        const Launch& lc) {
+                        float* part, int64_t nimg, int groups, int M, int mh, int rb, unsigned bs, int w,
+                        int64_t* ntiles_out, const Launch& lc) {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     using C = GradCfg<L>;
+    if (mh % w || mh < M / 2 + 1) return hipErrorInvalidValue;
     const int lds = std::max(C::TWB + w * C::region(w), (int)(w * TPT * sizeof(float)));
-    const int ctiles = M / w;
+    const int tiles = mh / w;
     const int per_group = (int)((nimg + groups - 1) / groups);
-    const int64_t ntiles = (int64_t)groups * ctiles;
+    const int64_t ntiles = (int64_t)groups * tiles;
     *ntiles_out = ntiles;
-    const int lt = ilog2c(ctiles);
     return go(k_cols_mse<L>, ntiles, w * TPT, lds, lc.stream, wsx, wsd, mask, sumx, sumxr, part, (int)nimg, per_group,
-              M, rb, bs, w, lt, (int)ntiles, twiddle_src<L, C>(lc));
+              M, mh, rb, bs, w, tiles, (int)ntiles, twiddle_src<L, C>(lc));
   }
 };
 
@@ -1572,7 +1590,7 @@ struct ColsStrided {
     return RowsXd<K>::run(x, c, wsx, wsd, blocks, rb, bs, lc);
 #define FFTMI_CASE_ColsMse(K) \
   case K:                     \
-    return ColsMse<K>::run(wsx, wsd, mask, sumx, sumxr, part, nimg, groups, M, rb, bs, w, ntiles, lc);
+    return ColsMse<K>::run(wsx, wsd, mask, sumx, sumxr, part, nimg, groups, M, mh, rb, bs, w, ntiles, lc);
 #define FFTMI_CASE_ColsStrided(K) \
   case K:                         \
     return ColsStrided<K>::run(inv, twiddle_transpose, in, out, batch, C, w, scale, tw_fs, in_bstride, in_rstride, \
@@ -1739,17 +1757,18 @@ hipError_t launch_rows_xd(int log2L, const float* x, const float* c, float2* wsx
 }
 
 hipError_t launch_cols_mse(int log2L, const float2* wsx, const float2* wsd, const float* mask, float* sumx,
-                           float* sumxr, float* part, int64_t nimg, int groups, int M, int rb, unsigned bs, int w,
-                           int64_t* ntiles, const Launch& lc) {
+                           float* sumxr, float* part, int64_t nimg, int groups, int M, int mh, int rb, unsigned bs,
+                           int w, int64_t* ntiles, const Launch& lc) {
   FFTMI_DISPATCH(ColsMse, log2L)
 }
 
-hipError_t launch_mse_grad_sums(const float* sumx, const float* sumxr, const float* mask, float* grad, int64_t n,
-                                int groups, float w, hipStream_t stream) {
+hipError_t launch_mse_grad_sums(const float* sumx, const float* sumxr, const float* mask, float* grad, int N, int M,
+                                int mh, int groups, float w, hipStream_t stream) {
+  const int64_t n = (int64_t)N * M;
   if (n <= 0) return hipSuccess;
   const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_mse_grad_sums, dim3((unsigned)blocks), dim3(256), 0, stream, sumx, sumxr, mask, grad, n, groups,
-                     w);
+  hipLaunchKernelGGL(k_mse_grad_sums, dim3((unsigned)blocks), dim3(256), 0, stream, sumx, sumxr, mask, grad, N, M, mh,
+                     groups, w);
   return hipGetLastError();
 }
 

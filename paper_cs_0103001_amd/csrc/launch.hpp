@@ -111,18 +111,21 @@ hipError_t launch_crop(const void* in, void* out, bool f32, int64_t nimg, int n0
 // blocked rows of each image in order, multiply by conj(saved spectrum X) and
 // accumulate the real part; part[g] = w_lin * sum + (mask ? w_sq * (m - 1) *
 // sum |X|^2 : 0).  With groups == 1, part may be the final gradient.
-// The filtered MSE in the frequency domain: row spectra of x and of x - c
-// from one complex transform per row (rb rows per tile, rb * TPT <= 1024),
-// then per run of images the column transforms, the loss terms (one sum per
-// tile in part[]) and the per-bin sums of |X|^2 and Re(conj X . R); the mask
-// gradient w * ((m - 1) sum|X|^2 + sum Re(conj X . R)) from those sums.
+// The filtered MSE in the frequency domain for real images: columns
+// 0 .. M/2 of the row spectra of x and of x - c from one complex transform
+// per row (rb rows per tile, rb * TPT <= 1024), in a blocked layout of mh
+// columns (block stride bs); then per run of images the column transforms,
+// the loss terms of each stored bin and its mirror (one sum per tile in
+// part[]) and the per-bin sums of |X|^2 and Re(conj X . R) ([N][mh] per
+// run); the mask gradient w * ((m - 1) sum|X|^2 + sum Re(conj X . R)) from
+// those sums, mirrored for v > M/2.
 hipError_t launch_rows_xd(int log2L, const float* x, const float* c, float2* wsx, float2* wsd, int64_t blocks, int rb,
                           unsigned bs, const Launch& lc);
 hipError_t launch_cols_mse(int log2L, const float2* wsx, const float2* wsd, const float* mask, float* sumx,
-                           float* sumxr, float* part, int64_t nimg, int groups, int M, int rb, unsigned bs, int w,
-                           int64_t* ntiles, const Launch& lc);
-hipError_t launch_mse_grad_sums(const float* sumx, const float* sumxr, const float* mask, float* grad, int64_t n,
-                                int groups, float w, hipStream_t stream);
+                           float* sumxr, float* part, int64_t nimg, int groups, int M, int mh, int rb, unsigned bs,
+                           int w, int64_t* ntiles, const Launch& lc);
+hipError_t launch_mse_grad_sums(const float* sumx, const float* sumxr, const float* mask, float* grad, int N, int M,
+                                int mh, int groups, float w, hipStream_t stream);
 hipError_t launch_cols_grad(int log2L, const float2* ws, const float2* save, const float* mask, float* part,
                             int64_t nimg, int groups, int M, int rb, unsigned bs, int w, float w_lin, float w_sq,
                             const Launch& lc);

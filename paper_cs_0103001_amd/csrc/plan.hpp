@@ -72,7 +72,12 @@ struct fftmi_plan {
   // offsets of their partial sums and of the fused MSE forward's per-tile sums
   int grad_groups = 1;
   size_t part_off = 0, loss_off = 0, loss_mid_off = 0;
-  size_t mse_sums_off = 0;  // in the saved-state buffer of the frequency-domain MSE
+  // the frequency-domain MSE: column tile width, stored columns (M/2 + 1
+  // rounded up to whole tiles), block stride and image size of its layout,
+  // and the offset of its per-bin sums in the caller's state buffer
+  int mse_w = 1, mse_mh = 0;
+  int64_t mse_bs = 0, mse_img = 0;
+  size_t mse_sums_off = 0;
   // rank 2 with columns of 2048 points or more (tiles of one or two columns):
   // workspace offset of a transposed copy of a tensor mask (0: none)
   size_t maskt_off = 0;

@@ -80,7 +80,9 @@ def test_padded_sizes_cover_layout():
     n, m, batch = 256, 4096, 3
     plan = api.Plan(2, (n, m), batch, B.FFT_IN_REAL_F32, torch.device("cuda", 0))
     blocked = batch * (n // 4) * (4 * m + 32) * 8
-    assert plan.spectrum_bytes == blocked
+    # the saved spectrum, or the state of the frequency-domain MSE (row
+    # spectra of x - c and per-bin sums), whichever is larger
+    assert plan.spectrum_bytes >= blocked
     assert plan.workspace_bytes >= blocked
 
 
