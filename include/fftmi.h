@@ -225,9 +225,11 @@ int fft2d_filter_mse_grad(fft_plan_t plan, const void* x, const void* c, const v
  *   loss[0] = weight * sum_b sum_{u,v} |(m - 1) X_b + R_b|^2 / (N M).
  * No inverse transform is taken and y is never formed.  One complex
  * transform per row of z = x + i (x - c) gives the row spectra of x and of
- * x - c (split by the Hermitian symmetry of real rows); the column pass
- * transforms both, adds the loss terms, and stores per run of images the
- * per-bin sums of |X|^2 and Re(conj X . R) in `state`.
+ * x - c (split by the Hermitian symmetry of real rows); x and c are real, so
+ * columns 0 .. M/2 carry every bin (X(N-u, M-v) = conj X(u, v)) and only
+ * those are stored and transformed along the columns; the column pass adds
+ * the loss terms of each stored bin and of its mirror and stores per run of
+ * images the per-bin sums of |X|^2 and Re(conj X . R) in `state`.
  *   x, c    float32 [B][N][M] (device), mask m float32 [N][M] (device)
  *   weight  e.g. 1 / (B N M) for the mean over all pixels
  *   state   fft_spectrum_size(plan) bytes (device, 16-byte aligned): the row
@@ -237,8 +239,9 @@ int fft2d_filter_mse_grad(fft_plan_t plan, const void* x, const void* c, const v
  * The workspace receives the row spectra of x.  The loss terms are summed in
  * float32 per thread over a run of images and in float64 across tiles, the
  * per-bin sums over each run of images in order (deterministic).  Errors as
- * fft2d_filter_mse; FFT_ERR_UNSUPPORTED also when rows per block times
- * threads per row transform exceeds 1024 (M > 4096 at four rows per block). */
+ * fft2d_filter_mse; FFT_ERR_UNSUPPORTED also for M < 4 and when rows per
+ * block times threads per row transform exceeds 1024 (M > 4096 at four rows
+ * per block). */
 int fft2d_filter_mse_spectral(fft_plan_t plan, const float* x, const float* c, const float* mask, float weight,
                               void* state, float* loss, void* workspace, void* stream);
 
@@ -246,7 +249,8 @@ int fft2d_filter_mse_spectral(fft_plan_t plan, const float* x, const float* c, c
  * fft2d_filter_mse_spectral with the same plan (any mask m, since the sums
  * do not depend on it):
  *   grad_mask = weight * ((m - 1) sum_b |X_b|^2 + sum_b Re(conj X_b . R_b)) / (N M)
- * with the runs added in order.  No transform is taken.  grad_mask float32
+ * with the runs added in order; a bin (u, v) with v > M/2 reads the sums of
+ * its mirror (N - u, M - v).  No transform is taken.  grad_mask float32
  * [N][M] (device, overwritten).  Errors as fft2d_filter_mse_spectral. */
 int fft2d_filter_mse_spectral_grad(fft_plan_t plan, const void* state, const float* mask, float weight,
                                    float* grad_mask, void* stream);
