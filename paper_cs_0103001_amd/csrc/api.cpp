@@ -394,8 +394,9 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       p->mse_mh = (int)((M / 2) / p->mse_w + 1) * p->mse_w;
       p->mse_bs = rb * p->mse_mh + fftmi::block_pad(rb * p->mse_mh);
       p->mse_img = (N / rb) * p->mse_bs;
+      p->mse_groups = fftmi::mse_groups(p->mse_mh / p->mse_w, batch);
       const int64_t nparts =
-          std::max<int64_t>({batch * N, (int64_t)p->grad_groups * (p->mse_mh / p->mse_w), (int64_t)1});
+          std::max<int64_t>({batch * N, (int64_t)p->mse_groups * (p->mse_mh / p->mse_w), (int64_t)1});
       p->loss_mid_off = (p->loss_off + (size_t)nparts * sizeof(float) + 255) & ~(size_t)255;
       p->ws_bytes = p->loss_mid_off + (size_t)sum_partials_scratch(nparts) * sizeof(double);
       // columns of 2048 points or more go in tiles of one or two columns, so
@@ -408,7 +409,7 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       // the frequency-domain MSE's state: the stored row spectra of x - c,
       // then the per-run sums of |X|^2 and Re(conj X . R) per stored bin
       p->mse_sums_off = ((size_t)batch * (size_t)p->mse_img * sizeof(float2) + 255) & ~(size_t)255;
-      p->spec_bytes = std::max(p->spec_bytes, p->mse_sums_off + 2 * (size_t)p->grad_groups * (size_t)N *
+      p->spec_bytes = std::max(p->spec_bytes, p->mse_sums_off + 2 * (size_t)p->mse_groups * (size_t)N *
                                                                     (size_t)p->mse_mh * sizeof(float));
     }
   }
@@ -831,14 +832,14 @@ int fft2d_filter_mse_spectral(fft_plan_t p, const float* x, const float* c, cons
   float2* wsx = static_cast<float2*>(workspace);
   float2* wsd = static_cast<float2*>(state);
   float* sumx = reinterpret_cast<float*>(static_cast<char*>(state) + p->mse_sums_off);
-  float* sumxr = sumx + (size_t)p->grad_groups * (size_t)p->n * (size_t)p->mse_mh;
+  float* sumxr = sumx + (size_t)p->mse_groups * (size_t)p->n * (size_t)p->mse_mh;
   const unsigned bs = (unsigned)p->mse_bs;
   Launch lr = launch_for(st, p->tables, p->log_m);
   Launch lcn = launch_for(st, p->tables, p->log_n);
   hipError_t e = launch_rows_xd(p->log_m, x, c, wsx, wsd, p->batch * p->n / p->rb, p->rb, bs, lr);
   if (e != hipSuccess) return hip_fail(e);
   int64_t nparts = 0;
-  e = launch_cols_mse(p->log_n, wsx, wsd, mask, sumx, sumxr, part, p->batch, p->grad_groups, (int)p->m, p->mse_mh,
+  e = launch_cols_mse(p->log_n, wsx, wsd, mask, sumx, sumxr, part, p->batch, p->mse_groups, (int)p->m, p->mse_mh,
                       p->rb, bs, p->mse_w, &nparts, lcn);
   if (e != hipSuccess) return hip_fail(e);
   e = launch_sum_partials(part, nparts, lw, loss, mid, st);
@@ -862,10 +863,10 @@ int fft2d_filter_mse_spectral_grad(fft_plan_t p, const void* state, const float*
     return e == hipSuccess ? FFT_OK : hip_fail(e);
   }
   const float* sumx = reinterpret_cast<const float*>(static_cast<const char*>(state) + p->mse_sums_off);
-  const float* sumxr = sumx + (size_t)p->grad_groups * (size_t)p->n * (size_t)p->mse_mh;
+  const float* sumxr = sumx + (size_t)p->mse_groups * (size_t)p->n * (size_t)p->mse_mh;
   // (weight / 2) d/dm sum |y - c|^2 = weight ((m - 1) sum |X|^2 + sum Re(conj X . R)) / (N M)
   const float gw = (float)((double)weight / ((double)p->n * (double)p->m));
-  hipError_t e = launch_mse_grad_sums(sumx, sumxr, mask, grad_mask, (int)p->n, (int)p->m, p->mse_mh, p->grad_groups,
+  hipError_t e = launch_mse_grad_sums(sumx, sumxr, mask, grad_mask, (int)p->n, (int)p->m, p->mse_mh, p->mse_groups,
                                       gw, st);
   return e == hipSuccess ? FFT_OK : hip_fail(e);
 }

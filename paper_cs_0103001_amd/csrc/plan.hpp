@@ -75,7 +75,7 @@ struct fftmi_plan {
   // the frequency-domain MSE: column tile width, stored columns (M/2 + 1
   // rounded up to whole tiles), block stride and image size of its layout,
   // and the offset of its per-bin sums in the caller's state buffer
-  int mse_w = 1, mse_mh = 0;
+  int mse_w = 1, mse_mh = 0, mse_groups = 1;
   int64_t mse_bs = 0, mse_img = 0;
   size_t mse_sums_off = 0;
   // rank 2 with columns of 2048 points or more (tiles of one or two columns):
@@ -118,6 +118,8 @@ int64_t filter_chunk(int64_t N, int64_t M, int64_t batch);
 // Image groups of the mask-gradient column pass: enough (column tile, group)
 // work items to fill the chip, each group a run of consecutive images.
 int grad_groups(int64_t col_tiles, int64_t batch);
+// Runs of images of the frequency-domain MSE's column pass.
+int mse_groups(int64_t col_tiles, int64_t batch);
 
 void destroy_ragged_state(fftmi_plan* p);
 void destroy_tree_state(fftmi_plan* p);

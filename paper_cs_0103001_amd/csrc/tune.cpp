@@ -12,6 +12,10 @@
 #include "launch.hpp"
 #include "plan.hpp"
 
+#ifndef FFTMI_MSE_TARGET_DEFAULT
+#define FFTMI_MSE_TARGET_DEFAULT 512
+#endif
+
 namespace fftmi {
 
 int widest_cols_tile(int log2L, int cols, int wmax, int max_threads) {
@@ -43,13 +47,11 @@ int64_t filter_chunk(int64_t N, int64_t M, int64_t batch) {
   return std::max<int64_t>(1, std::min(batch, c));
 }
 
-int grad_groups(int64_t col_tiles, int64_t batch) {
-  // work items (column tile, run of images): about two per CU, each over a
-  // long run.  Fewer, longer runs keep fewer images in flight at a time:
-  // batch 64 of 1024^2 took 304 / 258 / 246 / 293 us with runs of 8 / 16 /
-  // 32 / 64 images (non-temporal loads then took 32-image runs to 194 us).
-  int64_t target = 512;
-  if (const char* env = std::getenv("FFTMI_GRAD_TARGET")) {
+// Runs of consecutive images such that runs * col_tiles work items come to
+// at most `target` (an environment variable may set it), every run but the
+// last of the same length.
+static int run_groups(int64_t col_tiles, int64_t batch, int64_t target, const char* env_name) {
+  if (const char* env = std::getenv(env_name)) {
     const long long v = std::atoll(env);
     if (v >= 1 && v <= (1 << 20)) target = v;
   }
@@ -57,6 +59,21 @@ int grad_groups(int64_t col_tiles, int64_t batch) {
   int64_t g = std::max<int64_t>(1, std::min<int64_t>(batch, target / col_tiles));
   const int64_t per = (batch + g - 1) / g;
   return (int)((batch + per - 1) / per);
+}
+
+int grad_groups(int64_t col_tiles, int64_t batch) {
+  // work items (column tile, run of images): about two per CU, each over a
+  // long run.  Fewer, longer runs keep fewer images in flight at a time:
+  // batch 64 of 1024^2 took 304 / 258 / 246 / 293 us with runs of 8 / 16 /
+  // 32 / 64 images (non-temporal loads then took 32-image runs to 194 us).
+  return run_groups(col_tiles, batch, 512, "FFTMI_GRAD_TARGET");
+}
+
+int mse_groups(int64_t col_tiles, int64_t batch) {
+  // the frequency-domain MSE's column pass: as many work items as fit on the
+  // chip in one round (its column tiles per run, M / (2w) + 1, are not a
+  // power of two)
+  return run_groups(col_tiles, batch, FFTMI_MSE_TARGET_DEFAULT, "FFTMI_MSE_TARGET");
 }
 
 }  // namespace fftmi
