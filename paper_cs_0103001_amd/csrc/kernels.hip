@@ -946,7 +946,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
   const unsigned qs = (unsigned)(TPT / rb) * bs;
   const unsigned lane = (unsigned)ln.jh * bs + (unsigned)(ln.c * rb + ln.s);
   const int64_t plane = (int64_t)(L / rb) * bs;
-  float* red = reinterpret_cast<float*>(regions<L, C>());
+  double* red = reinterpret_cast<double*>(regions<L, C>());
   for (int n = blockIdx.x; n < ntiles; n += gridDim.x) {
     const int t = (int)tile_of(n, ntiles);
     const int g = t / tiles, ct = t - g * tiles;
@@ -966,7 +966,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
         ax[q] = axr[q] = 0.f;
       }
     }
-    float lacc = 0.f;
+    double lacc = 0.0;  // the loss terms of the tile, in double
     for (int bi = b0; bi < b1; ++bi) {
       float2 X[E], R[E];
       {
@@ -989,8 +989,8 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
         axr[q] = fmaf(X[q].x, R[q].x, fmaf(X[q].y, R[q].y, axr[q]));
         const float ex = fmaf(m1[q], X[q].x, R[q].x), ey = fmaf(m1[q], X[q].y, R[q].y);
         const float fx = fmaf(m2[q], X[q].x, R[q].x), fy = fmaf(m2[q], X[q].y, R[q].y);
-        lacc = fmaf(ex, ex, fmaf(ey, ey, lacc));
-        if (mir) lacc = fmaf(fx, fx, fmaf(fy, fy, lacc));
+        lacc += (double)fmaf(ex, ex, ey * ey);
+        if (mir) lacc += (double)fmaf(fx, fx, fy * fy);
       }
     }
     if (ok) {
@@ -1004,7 +1004,8 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
         dxr[f + q * qo] = axr[q];
       }
     }
-    // the tile's loss sum: an LDS tree over the workgroup, in a fixed order
+    // the tile's loss sum: an LDS tree over the workgroup, in a fixed order,
+    // in double
     const int tid = threadIdx.x;
     lds_barrier();  // the last transform's LDS reads are done
     red[tid] = lacc;
@@ -1013,7 +1014,7 @@ __global__ __launch_bounds__(Shape<L>::LB) void k_cols_mse(const float2* __restr
       if (tid < h) red[tid] += red[tid + h];
       lds_barrier();
     }
-    if (tid == 0) part[t] = red[0];
+    if (tid == 0) part[t] = (float)red[0];
     lds_barrier();  // red read before the next tile's transform reuses LDS
   }
 }
@@ -1502,7 +1503,7 @@ struct ColsMse {
     constexpr int L = 1 << LG, TPT = threads_per_transform(L);
     using C = GradCfg<L>;
     if (mh % w || mh < M / 2 + 1) return hipErrorInvalidValue;
-    const int lds = std::max(C::TWB + w * C::region(w), (int)(w * TPT * sizeof(float)));
+    const int lds = std::max(C::TWB + w * C::region(w), (int)(w * TPT * sizeof(double)));
     const int tiles = mh / w;
     const int per_group = (int)((nimg + groups - 1) / groups);
     const int64_t ntiles = (int64_t)groups * tiles;
