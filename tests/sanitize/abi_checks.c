@@ -105,6 +105,11 @@ int main(void) {
   EXPECT(fft2d_filter_mse_grad(NULL, p, NULL, p, (const float*)p, 1.0f, (float*)p, p, NULL), FFT_ERR_ARG);
   EXPECT(fft2d_filter_mse(bogus, (const float*)p, (const float*)p, (const float*)p, 1.0f, p, (float*)p, p, NULL),
          FFT_ERR_ARG);
+  EXPECT(fft2d_filter_mse_spectral(bogus, (const float*)p, (const float*)p, (const float*)p, 1.0f, p, (float*)p, p,
+                                   NULL),
+         FFT_ERR_ARG);
+  EXPECT(fft2d_filter_mse_spectral_grad(bogus, p, (const float*)p, 1.0f, (float*)p, NULL), FFT_ERR_ARG);
+  EXPECT(fft2d_filter_mse_spectral_grad(NULL, p, (const float*)p, 1.0f, (float*)p, NULL), FFT_ERR_ARG);
   EXPECT(fft2d_filter_ragged(bogus, p, p, NULL, p, NULL), FFT_ERR_ARG);
   EXPECT(fft_plan_tune(bogus, p, p, NULL, p, NULL), FFT_ERR_ARG);
   EXPECT(fft2d_spectrum(bogus, p, (float*)p, p, NULL), FFT_ERR_ARG);

@@ -82,6 +82,10 @@ def test_calls_reject_bad_plans():
     assert lib.fft2d_filter_mse_grad(bogus, p, p, p, p, 1.0, p, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_mse_grad(None, p, None, p, p, 1.0, p, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_mse(bogus, p, p, p, 1.0, p, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mse_spectral(bogus, p, p, p, 1.0, p, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mse_spectral(None, p, p, p, 1.0, p, p, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mse_spectral_grad(bogus, p, p, 1.0, p, None) == B.FFT_ERR_ARG
+    assert lib.fft2d_filter_mse_spectral_grad(None, p, p, 1.0, p, None) == B.FFT_ERR_ARG
     assert lib.fft2d_filter_ragged(bogus, p, p, None, p, None) == B.FFT_ERR_ARG
 
 
