@@ -48,8 +48,8 @@ enum { kPassRowsIn = 0, kPassCols = 1, kPassRowsOut = 2, kPassRows1D = 3 };
 // family.  One-pass 1D rows: 1 loads, 2 stores (stores only: 2^10..2^14 at
 // 6.4-6.6 / 5.7 / 4.7 TB/s against 5.0 / 4.3 / 3.9 without; loads too: less).
 // Ragged passes: 1 the first row pass's loads, 2 the column pass's loads, 4
-// the last row pass's loads (none: each was slower).  The four-step pass two
-// chooses at plan creation.
+// the last row pass's loads (none: each was slower).  The four-step passes
+// choose at plan creation.
 #ifndef FFTMI_NT_1D
 #define FFTMI_NT_1D 2
 #endif

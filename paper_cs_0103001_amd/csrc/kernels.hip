@@ -1063,8 +1063,8 @@ __global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ p
 // WIDE: tiles of up to 1024 threads (twice the columns of the 512-thread
 // tiles, so twice the contiguous bytes per row), with no prefetch, as the
 // 128 VGPRs a thread then has leave no room for a second tile.
-// nt (pass two): non-temporal loads of the intermediate and stores of the
-// result.
+// nt: pass one (1024-thread tiles), non-temporal loads of the input; pass
+// two, non-temporal loads of the intermediate and stores of the result.
 template <int L, bool INV, bool WIDE, bool TT>
 __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
     const float2* __restrict__ in, float2* __restrict__ out, int C, int w, int ltiles, int ntiles, float scale,
@@ -1083,6 +1083,10 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
   const unsigned lane = (unsigned)(j * irs + c);
   const int tmask = (1 << ltiles) - 1;
   constexpr bool PF = TPT <= 512 && !WIDE;  // 1024-thread workgroups have no room for a second tile
+  // pass one takes the hint in 1024-thread tiles only: with the register
+  // prefetch of the smaller tiles, a second load path costs VGPRs and a wave
+  // per SIMD
+  constexpr bool kHintsTT = TT && WIDE;
   float2 a[E], nx[PF ? E : 1];
   // tile t -> (batch entry, column tile).  Pass one takes the batch entries
   // of one column tile in a row (t = column tile * entries + entry), so that
@@ -1094,7 +1098,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
     const float2* b = in + (int64_t)entry_of(t) * ib + ctile_of(t) * w;
     const unsigned f_lane = fresh(lane);
-    if (!TT && nt) {
+    if (TT ? kHintsTT && nt != 0 : nt != 0) {
 #pragma unroll
       for (int q = 0; q < E; ++q) d[q] = ld_nt(b, f_lane + q * qs);
     } else {
@@ -1531,7 +1535,7 @@ struct ColsStrided {
                : go_one<INV, WIDE, false>(in, out, ntiles, w, lds, C, lt, scale, tfs, tw, ib, irs, ob, ors, nt, lc);
   }
   static hipError_t run(bool inv, bool twt, const float2* in, float2* out, int64_t batch, int C, int w, float scale,
-                        const float2* tfs, int64_t ib, int irs, int64_t ob, int ors, bool nt, const Launch& lc) {
+                        const float2* tfs, int64_t ib, int irs, int64_t ob, int ors, int nt, const Launch& lc) {
     // the four-step splits use column lengths 2^7 .. 2^12 only
     if constexpr (LG < 7 || LG > 12) {
       return hipErrorInvalidValue;
@@ -1785,7 +1789,7 @@ hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int grou
 
 hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,
                                int64_t batch, int C, int w, float scale, const float2* tw_fs, int64_t in_bstride,
-                               int in_rstride, int64_t out_bstride, int out_rstride, bool nt, const Launch& lc) {
+                               int in_rstride, int64_t out_bstride, int out_rstride, int nt, const Launch& lc) {
   FFTMI_DISPATCH(ColsStrided, log2L)
 }
 

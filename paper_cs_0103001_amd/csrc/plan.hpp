@@ -65,6 +65,7 @@ struct fftmi_plan {
   int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1;
   int fs_rs = 0;  // row stride of the [N2][N1] intermediate (N1 + pad)
   bool fs_nt = false;  // pass two with non-temporal loads and stores
+  bool fs_nt1 = false;  // pass one with non-temporal loads
   int64_t fs_chunk = 1;  // batch entries per chunk of the two passes
   const float2* tw_fs = nullptr;  // [N2][N1] factors W_N^{k1 n2}
   size_t ws_bytes = 0, spec_bytes = 0;

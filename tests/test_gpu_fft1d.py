@@ -96,7 +96,7 @@ def test_deterministic():
 
 
 _FS_KNOBS = ("FFTMI_FS_PAD", "FFTMI_FS_W", "FFTMI_FS_THREADS1", "FFTMI_FS_THREADS2", "FFTMI_FS_LOG_N1", "FFTMI_FS_NT",
-             "FFTMI_FS_CHUNK_MB")
+             "FFTMI_FS_NT1", "FFTMI_FS_CHUNK_MB")
 
 
 def _fft_with(env, x, direction):
@@ -172,21 +172,24 @@ def test_fourstep_wide_tiles(lg):
 
 
 @pytest.mark.parametrize("lg", [16, 20, 21])
-def test_fourstep_nontemporal_pass_two(lg):
-    """Pass two with and without the non-temporal loads and stores (on by
-    default up to 2^20 points): cache hints only, so both are bit-identical
-    and match the oracle in both directions."""
+def test_fourstep_nontemporal_hints(lg):
+    """Pass two with and without its non-temporal loads and stores (on by
+    default up to 2^20 points), and pass one with and without its
+    non-temporal input loads (1024-thread tiles, from 2^20 points): cache
+    hints only, so every combination is bit-identical and matches the oracle
+    in both directions."""
     from paper_cs_0103001_amd import _binding as B
     x = synth.uniform_complex((2, 1 << lg), (16, lg))
     xd = to_dev(x)
     for direction, ref in ((B.FFT_FORWARD, oracle.fft(x, threads=8)), (B.FFT_INVERSE, oracle.ifft(x, threads=8))):
         outs = []
-        for nt in (0, 1):
-            announce("fft1d four-step n=2^%d dir %d non-temporal pass two %d" % (lg, direction, nt))
-            got, _ = _fft_with(dict(FFTMI_FS_NT=nt), xd, direction)
-            assert rel_l2(got, ref, 1) < TOL, nt
+        for nt, nt1 in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            announce("fft1d four-step n=2^%d dir %d non-temporal pass two %d pass one %d" % (lg, direction, nt, nt1))
+            got, _ = _fft_with(dict(FFTMI_FS_NT=nt, FFTMI_FS_NT1=nt1), xd, direction)
+            assert rel_l2(got, ref, 1) < TOL, (nt, nt1)
             outs.append(got)
-        assert np.array_equal(outs[0], outs[1])
+        for o in outs[1:]:
+            assert np.array_equal(outs[0], o)
 
 
 @pytest.mark.parametrize("lg", [16, 19])
