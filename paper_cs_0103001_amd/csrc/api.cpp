@@ -347,18 +347,19 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       if (const char* e = std::getenv("FFTMI_FS_NT")) p->fs_nt = std::atoi(e) != 0;
       p->ws_bytes = (size_t)batch * (size_t)(1 << p->log_n2) * (size_t)p->fs_rs * sizeof(float2);
       // batch entries per chunk: about FFTMI_FS_CHUNK_MB MiB of intermediate
-      // (default 128 up to 2^20 points: 2^15..2^17 +8-12%, 2^19..2^20 +2%;
-      // at 2^21 it lost 1-2%, so the whole batch there); 0: the whole batch
+      // (default 128: 2^15..2^17 +8-12%, 2^19..2^20 +2%, and with pass one's
+      // non-temporal loads below, 2^21 and 2^22 +14%); 0: the whole batch
       {
-        int64_t mib = p->log_n <= 20 ? 128 : 0;
+        int64_t mib = 128;
         if (const char* e = std::getenv("FFTMI_FS_CHUNK_MB")) mib = std::atoll(e);
         const int64_t per_entry = (int64_t)(1 << p->log_n2) * p->fs_rs * (int64_t)sizeof(float2);
         p->fs_chunk = mib > 0 ? std::max<int64_t>(1, std::min<int64_t>(batch, (mib << 20) / per_entry))
                               : std::max<int64_t>(batch, 1);
         // pass one with non-temporal loads of the input while the chunk's
         // intermediate fits the memory-side cache, so the input read once
-        // does not evict what pass two reads next (+6-7% at 2^20; the
-        // 512-thread tiles below take no hint); FFTMI_FS_NT1=0/1 forces
+        // does not evict what pass two reads next (+6-7% at 2^20, and what
+        // makes the chunks pay at 2^21 and 2^22; the 512-thread tiles below
+        // 2^20 take no hint); FFTMI_FS_NT1=0/1 forces
         const int64_t inter = p->fs_chunk * per_entry;
         p->fs_nt1 = inter <= (int64_t(128) << 20);
         if (const char* e = std::getenv("FFTMI_FS_NT1")) p->fs_nt1 = std::atoi(e) != 0;

@@ -192,7 +192,7 @@ def test_fourstep_nontemporal_hints(lg):
             assert np.array_equal(outs[0], o)
 
 
-@pytest.mark.parametrize("lg", [16, 19])
+@pytest.mark.parametrize("lg", [16, 19, 21])
 def test_fourstep_chunks(lg):
     """The batch in chunks of batch entries (each chunk's two passes reuse the
     start of the workspace), including a last chunk shorter than the others:
