@@ -341,10 +341,12 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       // the intermediate [N2][N1] rows get a padded stride, so that the
       // second pass's column reads do not all land on the same channels
       p->fs_rs = (1 << p->log_n1) + fourstep_pad(p->log_n1);
-      // pass two with non-temporal loads and stores up to 2^20 points
-      // (+3-7% there, 4-10% slower at 2^21 and 2^22); FFTMI_FS_NT=0/1 forces
-      p->fs_nt = p->log_n <= 20;
-      if (const char* e = std::getenv("FFTMI_FS_NT")) p->fs_nt = std::atoi(e) != 0;
+      // pass two with non-temporal stores of the result up to 2^20 points
+      // (+3-4% at 2^15..2^18 against stores and loads together, which the
+      // chunks' cached intermediate does not need; 4-6% slower at 2^21 and
+      // 2^22); FFTMI_FS_NT = 0..3 forces (1 loads, 2 stores)
+      p->fs_nt = p->log_n <= 20 ? 2 : 0;
+      if (const char* e = std::getenv("FFTMI_FS_NT")) p->fs_nt = std::atoi(e) & 3;
       p->ws_bytes = (size_t)batch * (size_t)(1 << p->log_n2) * (size_t)p->fs_rs * sizeof(float2);
       // batch entries per chunk: about FFTMI_FS_CHUNK_MB MiB of intermediate
       // (default 128: 2^15..2^17 +8-12%, 2^19..2^20 +2%, and with pass one's
@@ -558,7 +560,7 @@ int fft_exec(fft_plan_t p, const void* in, void* out, void* workspace, int direc
                               1.0f, p->tw_fs, p->n, n2, wsb, p->fs_rs, p->fs_nt1 ? 1 : 0, l1);
       if (e != hipSuccess) return hip_fail(e);
       e = launch_cols_strided(p->log_n2, inv_tw, false, ws, static_cast<float2*>(out) + b0 * p->n, nb, n1, p->w2,
-                              scale, nullptr, wsb, p->fs_rs, p->n, n1, p->fs_nt ? 1 : 0, l2);
+                              scale, nullptr, wsb, p->fs_rs, p->n, n1, p->fs_nt, l2);
       if (e != hipSuccess) return hip_fail(e);
     }
     return FFT_OK;

@@ -1063,8 +1063,9 @@ __global__ __launch_bounds__(256) void k_sum_groups(const float4* __restrict__ p
 // WIDE: tiles of up to 1024 threads (twice the columns of the 512-thread
 // tiles, so twice the contiguous bytes per row), with no prefetch, as the
 // 128 VGPRs a thread then has leave no room for a second tile.
-// nt: pass one (1024-thread tiles), non-temporal loads of the input; pass
-// two, non-temporal loads of the intermediate and stores of the result.
+// nt: bit 1 non-temporal loads (pass one: of the input, in 1024-thread
+// tiles only; pass two: of the intermediate), bit 2 (pass two) non-temporal
+// stores of the result.
 template <int L, bool INV, bool WIDE, bool TT>
 __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
     const float2* __restrict__ in, float2* __restrict__ out, int C, int w, int ltiles, int ntiles, float scale,
@@ -1098,7 +1099,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
   auto load = [&](float2(&d)[E], int t) __attribute__((always_inline)) {
     const float2* b = in + (int64_t)entry_of(t) * ib + ctile_of(t) * w;
     const unsigned f_lane = fresh(lane);
-    if (TT ? kHintsTT && nt != 0 : nt != 0) {
+    if ((!TT || kHintsTT) && (nt & 1) != 0) {
 #pragma unroll
       for (int q = 0; q < E; ++q) d[q] = ld_nt(b, f_lane + q * qs);
     } else {
@@ -1171,7 +1172,7 @@ __global__ __launch_bounds__(WIDE ? 1024 : Shape<L>::LB) void k_cols_strided(
       {
         const unsigned f_lane = fresh((unsigned)(j * ors + c));
         const unsigned oqs = (unsigned)(TPT * ors);
-        if (nt) {
+        if (nt & 2) {
 #pragma unroll
           for (int q = 0; q < E; ++q) st_nt(b + f_lane + q * oqs, cscale(a[q], scale));
         } else {

@@ -138,9 +138,9 @@ hipError_t launch_sum_groups(const float* part, float* grad, int64_t n, int grou
 // r*in_rstride), tiles of w columns.  twiddle_transpose: pass one (multiply by
 // W_N^{k1 n2}, N = L*C, from tw_fs[n2*L + k1], and store column c as the
 // contiguous row out + b*out_bstride + c*out_rstride); otherwise pass two
-// (store [L][C] with row stride out_rstride; tw_fs unused).  nt: pass one,
-// non-temporal loads (1024-thread tiles only); pass two, non-temporal loads
-// and stores.
+// (store [L][C] with row stride out_rstride; tw_fs unused).  nt: bit 1
+// non-temporal loads (pass one: 1024-thread tiles only), bit 2 (pass two)
+// non-temporal stores.
 hipError_t launch_cols_strided(int log2L, bool inv, bool twiddle_transpose, const float2* in, float2* out,
                                int64_t batch, int C, int w, float scale, const float2* tw_fs, int64_t in_bstride,
                                int in_rstride, int64_t out_bstride, int out_rstride, int nt, const Launch& lc);

@@ -64,7 +64,7 @@ struct fftmi_plan {
   bool fourstep = false;
   int log_n1 = 0, log_n2 = 0, w1 = 1, w2 = 1;
   int fs_rs = 0;  // row stride of the [N2][N1] intermediate (N1 + pad)
-  bool fs_nt = false;  // pass two with non-temporal loads and stores
+  int fs_nt = 0;       // pass two: 1 non-temporal loads, 2 non-temporal stores
   bool fs_nt1 = false;  // pass one with non-temporal loads
   int64_t fs_chunk = 1;  // batch entries per chunk of the two passes
   const float2* tw_fs = nullptr;  // [N2][N1] factors W_N^{k1 n2}

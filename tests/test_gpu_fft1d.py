@@ -173,17 +173,17 @@ def test_fourstep_wide_tiles(lg):
 
 @pytest.mark.parametrize("lg", [16, 20, 21])
 def test_fourstep_nontemporal_hints(lg):
-    """Pass two with and without its non-temporal loads and stores (on by
-    default up to 2^20 points), and pass one with and without its
-    non-temporal input loads (1024-thread tiles, from 2^20 points): cache
-    hints only, so every combination is bit-identical and matches the oracle
-    in both directions."""
+    """Pass two with none, either or both of its non-temporal loads and
+    stores (both by default up to 2^20 points), and pass one with and
+    without its non-temporal input loads (1024-thread tiles, from 2^20
+    points): cache hints only, so every combination is bit-identical and
+    matches the oracle in both directions."""
     from paper_cs_0103001_amd import _binding as B
     x = synth.uniform_complex((2, 1 << lg), (16, lg))
     xd = to_dev(x)
     for direction, ref in ((B.FFT_FORWARD, oracle.fft(x, threads=8)), (B.FFT_INVERSE, oracle.ifft(x, threads=8))):
         outs = []
-        for nt, nt1 in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        for nt, nt1 in ((0, 0), (1, 0), (2, 0), (3, 0), (0, 1), (3, 1)):
             announce("fft1d four-step n=2^%d dir %d non-temporal pass two %d pass one %d" % (lg, direction, nt, nt1))
             got, _ = _fft_with(dict(FFTMI_FS_NT=nt, FFTMI_FS_NT1=nt1), xd, direction)
             assert rel_l2(got, ref, 1) < TOL, (nt, nt1)
