@@ -347,7 +347,6 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       // 2^22); FFTMI_FS_NT = 0..3 forces (1 loads, 2 stores)
       p->fs_nt = p->log_n <= 20 ? 2 : 0;
       if (const char* e = std::getenv("FFTMI_FS_NT")) p->fs_nt = std::atoi(e) & 3;
-      p->ws_bytes = (size_t)batch * (size_t)(1 << p->log_n2) * (size_t)p->fs_rs * sizeof(float2);
       // batch entries per chunk: about FFTMI_FS_CHUNK_MB MiB of intermediate
       // (default 128: 2^15..2^17 +8-12%, 2^19..2^20 +2%, and with pass one's
       // non-temporal loads below, 2^21 and 2^22 +14%); 0: the whole batch
@@ -357,6 +356,8 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
         const int64_t per_entry = (int64_t)(1 << p->log_n2) * p->fs_rs * (int64_t)sizeof(float2);
         p->fs_chunk = mib > 0 ? std::max<int64_t>(1, std::min<int64_t>(batch, (mib << 20) / per_entry))
                               : std::max<int64_t>(batch, 1);
+        // every chunk reuses the start of the workspace
+        p->ws_bytes = (size_t)std::min<int64_t>(batch, p->fs_chunk) * (size_t)per_entry;
         // pass one with non-temporal loads of the input while the chunk's
         // intermediate fits the memory-side cache, so the input read once
         // does not evict what pass two reads next (+6-7% at 2^20, and what

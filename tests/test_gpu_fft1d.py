@@ -195,22 +195,30 @@ def test_fourstep_nontemporal_hints(lg):
 @pytest.mark.parametrize("lg", [16, 19, 21])
 def test_fourstep_chunks(lg):
     """The batch in chunks of batch entries (each chunk's two passes reuse the
-    start of the workspace), including a last chunk shorter than the others:
-    bit-identical to the whole batch at once, and the oracle's result."""
+    start of the workspace, which holds one chunk), including a last chunk
+    shorter than the others: bit-identical to the whole batch at once, and
+    the oracle's result."""
     from paper_cs_0103001_amd import _binding as B
     batch = 5
     x = synth.uniform_complex((batch, 1 << lg), (17, lg))
     xd = to_dev(x)
     per_entry_mib = (1 << lg) * 8 / float(1 << 20)
     for direction, ref in ((B.FFT_FORWARD, oracle.fft(x, threads=8)), (B.FFT_INVERSE, oracle.ifft(x, threads=8))):
-        outs = []
-        for mib in (0, int(2 * per_entry_mib) + 1, 128):  # whole batch, chunks of 2-3 entries, default
+        outs, ws = [], []
+        for mib in (0, int(2 * per_entry_mib) + 1, 128):  # whole batch, chunks of 2-4 entries, default
             announce("fft1d four-step n=2^%d batch %d chunk %d MiB dir %d" % (lg, batch, mib, direction))
-            got, _ = _fft_with(dict(FFTMI_FS_CHUNK_MB=mib), xd, direction)
+            got, plan = _fft_with(dict(FFTMI_FS_CHUNK_MB=mib), xd, direction)
             assert rel_l2(got, ref, 1) < TOL, (mib, direction)
             outs.append(got)
+            ws.append(B.fft_workspace_size(plan.h))
         for o in outs[1:]:
             assert np.array_equal(o, outs[0])
+        # the workspace holds one chunk: a whole number of the entries of the
+        # whole-batch plan's, fewer of them for the smaller chunks
+        per_entry = ws[0] // batch
+        assert ws[0] == per_entry * batch and per_entry >= (1 << lg) * 8
+        assert ws[1] % per_entry == 0 and ws[1] < ws[0]
+        assert ws[2] % per_entry == 0 and ws[2] <= ws[0]
 
 
 @pytest.mark.parametrize("lg", [15, 20, 22])
