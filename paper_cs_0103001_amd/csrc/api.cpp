@@ -366,9 +366,9 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
         p->ws_bytes = (size_t)std::min<int64_t>(batch, p->fs_chunk) * (size_t)per_entry;
         // pass one with non-temporal loads of the input while the chunk's
         // intermediate fits the memory-side cache, so the input read once
-        // does not evict what pass two reads next (+6-7% at 2^20, and what
-        // makes the chunks pay at 2^21 and 2^22; the 512-thread tiles below
-        // 2^20 take no hint); FFTMI_FS_NT1=0/1 forces
+        // does not evict what pass two reads next: what makes the chunks pay
+        // at 2^21 and 2^22 (1024-thread tiles only; the 512-thread tiles up
+        // to 2^20 take no hint); FFTMI_FS_NT1=0/1 forces
         const int64_t inter = p->fs_chunk * per_entry;
         p->fs_nt1 = inter <= (int64_t(128) << 20);
         if (const char* e = std::getenv("FFTMI_FS_NT1")) p->fs_nt1 = std::atoi(e) != 0;
