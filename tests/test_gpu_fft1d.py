@@ -174,9 +174,9 @@ def test_fourstep_wide_tiles(lg):
 @pytest.mark.parametrize("lg", [16, 20, 21])
 def test_fourstep_nontemporal_hints(lg):
     """Pass two with none, either or both of its non-temporal loads and
-    stores (both by default up to 2^20 points), and pass one with and
-    without its non-temporal input loads (1024-thread tiles, from 2^20
-    points): cache hints only, so every combination is bit-identical and
+    stores (stores by default up to 2^20 points), and pass one with and
+    without its non-temporal input loads (taken by its 1024-thread tiles,
+    2^21 here): cache hints only, so every combination is bit-identical and
     matches the oracle in both directions."""
     from paper_cs_0103001_amd import _binding as B
     x = synth.uniform_complex((2, 1 << lg), (16, lg))
