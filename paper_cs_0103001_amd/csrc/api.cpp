@@ -355,9 +355,11 @@ int fft_plan(fft_plan_t* out, int rank, const int64_t* dims, int64_t batch, uint
       if (const char* e = std::getenv("FFTMI_FS_NT")) p->fs_nt = std::atoi(e) & 3;
       // batch entries per chunk: about FFTMI_FS_CHUNK_MB MiB of intermediate
       // (default 128: 2^15..2^17 +8-12%, 2^19..2^20 +2%, and with pass one's
-      // non-temporal loads below, 2^21 and 2^22 +14%); 0: the whole batch
+      // non-temporal loads below, 2^21 and 2^22 +14%; 112 from 2^21, which
+      // leaves more of the cache to pass one's 16-32 MiB factor table: 2^21
+      // +3%); 0: the whole batch
       {
-        int64_t mib = 128;
+        int64_t mib = p->log_n >= 21 ? 112 : 128;
         if (const char* e = std::getenv("FFTMI_FS_CHUNK_MB")) mib = std::atoll(e);
         const int64_t per_entry = (int64_t)(1 << p->log_n2) * p->fs_rs * (int64_t)sizeof(float2);
         p->fs_chunk = mib > 0 ? std::max<int64_t>(1, std::min<int64_t>(batch, (mib << 20) / per_entry))
